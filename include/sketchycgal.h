@@ -1,0 +1,183 @@
+/*
+ * sketchycgal.h -- C ABI of the MI355X (gfx950) SketchyCGAL library for the
+ * MaxCut SDP.
+ *
+ * The library solves the model problem of Section 2.1 (eqn model-problem)
+ *
+ *     minimize <C, X>  subject to  diag(X) = b,  X psd,  tr X = alpha,
+ *
+ * which for C = -L/4 (L the weighted graph Laplacian, eqn comb-laplacian)
+ * and b = 1 is the MaxCut SDP (Section 1.1, eqn maxcut-sdp) with
+ * alpha = sum(b) = n.  It runs SketchyCGAL (Section 6, alg:sketchy-cgal):
+ * the n x n variable is never formed; the iteration keeps z = diag(X)
+ * (primitive 3 of eqn primitives), the dual y, the objective tracker p and a
+ * Nystrom sketch S = X Omega (Section 5).  C is touched only through sparse
+ * matrix-vector products (primitives 1 and 2).
+ *
+ * Conventions for every entry point:
+ *   - Arrays marked "device" are hipMalloc'd (or torch CUDA) pointers on the
+ *     current HIP device; arrays marked "host" are ordinary host memory.
+ *   - Every function returns scg_status and never throws across the ABI.
+ *   - A context is used by one host thread at a time; all its GPU work is
+ *     enqueued on the stream given to sketchycgal_init.
+ *   - The library never calls hipMalloc/hipFree after init: the caller owns
+ *     every device buffer, including the workspace.
+ *   - Values inside the iteration are in scaled units (Section 7.1.1, eqn
+ *     problem-scaling: ||C||_F = 1, alpha = 1, b <- b / alpha) when
+ *     params.scale = 1; sketchycgal_summary converts back.
+ */
+#ifndef SKETCHYCGAL_H
+#define SKETCHYCGAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCG_OK = 0,
+    SCG_EINVAL = 1,    /* bad argument or malformed CSR                          */
+    SCG_ENOMEM = 2,    /* workspace smaller than scg_workspace_size reports      */
+    SCG_EHIP = 3,      /* a HIP runtime call failed                             */
+    SCG_ENUMERIC = 4,  /* NaN/Inf in the iteration, or Cholesky failed (reconstruct) */
+    SCG_ESTATE = 5     /* stepping past T, or a call out of order               */
+} scg_status;
+
+typedef enum {
+    SCG_FP64 = 0,         /* every stream and accumulator in FP64 ("plain FP64")                */
+    SCG_FP32_STREAM = 1   /* matrix, Lanczos basis, Omega, S stored/streamed in FP32 with FP32
+                             SpMV accumulation; tridiagonal eigensolve, z, y, p, dot products and
+                             the reconstruction in FP64 */
+} scg_precision;
+
+/* Solver parameters; scg_default_params fills the paper's defaults
+ * (Section 7.1.2: beta0 = 1, K = +inf, Gaussian Omega, trace correction on,
+ * scaling on; q_t = t^(1/4) log n from alg:sketchy-cgal). */
+typedef struct {
+    int32_t  R;             /* sketch size, 1 <= R <= min(n, 32)                           */
+    int32_t  T;             /* iteration budget (sizes logs and the Lanczos basis), >= 1    */
+    double   beta0;         /* initial smoothing beta0 > 0 (beta_t = beta0 sqrt(t+1))        */
+    double   K;             /* dual bound K >= 0; +INF disables the guard                   */
+    double   alpha;         /* trace alpha > 0; <= 0 selects sum(b)                          */
+    uint64_t seed;          /* Philox4x64-10 key for Omega and the Lanczos start vectors     */
+    int32_t  q_mode;        /* 0: q_t = ceil(t^(1/4) ln n); 1: q_t = q_fixed                 */
+    int32_t  q_fixed;       /* used when q_mode = 1                                          */
+    int32_t  scale;         /* 1: scale the problem (Section 7.1.1); 0: solve as given       */
+    int32_t  trace_correct; /* 1: trace-correct Lambda in reconstruct (alg:sketchy-cgal)     */
+    int32_t  reorth;        /* 0: Lanczos as in alg:rand-lanczos; 2: full reorthogonalisation */
+    int32_t  precision;     /* scg_precision                                                 */
+    int32_t  instance;      /* Philox counter word selecting this problem's random streams   */
+} scg_params;
+
+/* One record per iteration t, in scaled units (see file comment).  Gap and
+ * stopping quantities use the state before the update (Section 6.2 and
+ * Appendix E, eqn scgal-stopping-supp, with lambda_min(D_t) ~ xi_t). */
+typedef struct {
+    int32_t t, q, k, flags;   /* iteration, Lanczos cap q_t, Lanczos steps taken, bit0 = breakdown */
+    double xi;                /* Ritz value (approximate lambda_min(D_t))                          */
+    double cv;                /* v^T C v                                                           */
+    double p;                 /* p_{t+1} = <C, X_{t+1}>                                            */
+    double infeas;            /* ||z_{t+1} - b||                                                   */
+    double gamma;             /* dual step taken (0 when the K guard refused it)                   */
+    double gap;               /* surrogate duality gap g_t                                         */
+    double stop_obj;          /* relative-gap stopping quantity                                    */
+    double stop_feas;         /* ||z_t - b|| / (1 + ||b||)                                         */
+    double resid;             /* ||D_t v - xi v||                                                  */
+    double beta, eta;
+} scg_iter_log;
+
+/* Result summary in ORIGINAL units (objective <C, X_T>, infeasibility
+ * ||diag X_T - b||) plus the scaling constants. */
+typedef struct {
+    int32_t t_done;           /* iterations completed                       */
+    int32_t status_flags;     /* bit0: NaN/Inf seen                         */
+    double objective;         /* <C, X>                                     */
+    double infeasibility;     /* ||diag X - b||                             */
+    double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
+} scg_summary;
+
+typedef struct scg_ctx scg_ctx;
+
+/* Fill *p with the defaults above (R = 10, T = 100, seed = 0, FP64). */
+void scg_default_params(scg_params* p);
+
+/* Bytes of device workspace sketchycgal_init needs for an n x n matrix with
+ * at most nnz stored entries (diagonal included). */
+scg_status scg_workspace_size(const scg_params* p, int64_t n, int64_t nnz, size_t* bytes);
+
+/* Create a context and run the initialisation of alg:sketchy-cgal:
+ * validate and scale the data, split the diagonal of C from its off-diagonal
+ * part, draw Omega (NystromSketch.Init), zero z, y, S, tau, p.
+ *   row_ptr  device int64[n+1], row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz
+ *   col      device int32[nnz], 0 <= col < n (order within a row is free)
+ *   val      device double[nnz], finite; C must be symmetric (not checked)
+ *   b        device double[n], finite
+ *   omega    device double[n*R] row-major test matrix, or NULL to draw it from
+ *            the Philox stream (seed; column c, instance, purpose 1)
+ *   workspace device, at least scg_workspace_size bytes, 256-byte aligned,
+ *            owned by the caller and kept alive until sketchycgal_destroy
+ *   stream   hipStream_t (NULL = default stream)
+ * Inputs are copied; they may be freed after init returns.  init
+ * synchronises the stream once (validation).  Errors: SCG_EINVAL for bad
+ * sizes/parameters/CSR/non-finite data, SCG_ENOMEM for a short workspace,
+ * SCG_EHIP for runtime failures; *out is NULL on error. */
+scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64_t nnz,
+                            const int64_t* row_ptr, const int32_t* col, const double* val,
+                            const double* b, const double* omega, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/* Enqueue `iters` iterations of alg:sketchy-cgal (loop body: ApproxMinEvec by
+ * randomized Lanczos, z, y and sketch updates).  Asynchronous: never
+ * synchronises.  SCG_ESTATE if it would run past T. */
+scg_status sketchycgal_step(scg_ctx* ctx, int32_t iters);
+
+/* NystromSketch.Reconstruct (alg:nystrom-sketch-supp) of the current sketch,
+ * in FP64 on the device, with the optional trace correction of
+ * alg:sketchy-cgal.  X_hat = U diag(lambda) U^T approximates X in SCALED
+ * units (multiply lambda by alpha/alpha_scaled for the original X).
+ *   U       device double[n*R] column-major (column j contiguous), orthonormal
+ *   lambda  device double[R], nonincreasing, >= 0 (trace-corrected if enabled)
+ *   err     device double[R] or NULL: err_r = tau - sum_{j<=r} lambda_raw_j
+ *           (eqn sketch-err-supp)
+ * Synchronises the stream.  SCG_ENUMERIC if Cholesky fails after three
+ * tenfold increases of the shift. */
+scg_status sketchycgal_reconstruct(scg_ctx* ctx, double* U, double* lambda, double* err);
+
+/* Copy up to `max` iteration records into host memory (synchronises). */
+scg_status sketchycgal_log(scg_ctx* ctx, scg_iter_log* host_out, int32_t max, int32_t* count);
+
+/* Summary in original units (synchronises).  SCG_ENUMERIC if NaN/Inf seen. */
+scg_status sketchycgal_summary(scg_ctx* ctx, scg_summary* host_out);
+
+/* Checkpoint / resume of the iteration state (scaled units; device arrays):
+ * z, y double[n]; S double[n*R] row-major; t_next is the next iteration
+ * index (1 = fresh).  get_state synchronises. */
+scg_status sketchycgal_get_state(scg_ctx* ctx, int32_t* t_next, double* z, double* y, double* S,
+                                 double* p, double* tau);
+scg_status sketchycgal_set_state(scg_ctx* ctx, int32_t t_next, const double* z, const double* y,
+                                 const double* S, double p, double tau);
+
+/* Tridiagonal coefficients of the last Lanczos run (host arrays of length
+ * >= *k on return): omega[0..k), rho[0..k-1), and its Ritz value.
+ * Synchronises. */
+scg_status sketchycgal_lanczos_coeffs(scg_ctx* ctx, double* omega, double* rho, int32_t cap,
+                                      int32_t* k, double* xi);
+
+/* x -> D x with D = C_s + diag(y + beta_t (z - b)) for the next iteration t
+ * (primitives 1 and 2 of eqn primitives; device double[n] in and out), using
+ * the same SpMV kernel as the Lanczos loop.  Synchronises. */
+scg_status sketchycgal_apply(scg_ctx* ctx, const double* x, double* y);
+
+/* Average duration (ms) of `reps` back-to-back launches of the Lanczos SpMV
+ * kernel on the context's stream, timed with HIP events on that stream. */
+scg_status sketchycgal_time_spmv(scg_ctx* ctx, int32_t reps, double* avg_ms);
+
+void sketchycgal_destroy(scg_ctx* ctx);
+const char* scg_status_string(scg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKETCHYCGAL_H */

@@ -1,0 +1,169 @@
+"""Python front end of the SketchyCGAL library (marshalling only).
+
+Device buffers are torch CUDA tensors; every computation happens in the HIP
+library through the C ABI of include/sketchycgal.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+@dataclasses.dataclass
+class Params:
+    """Mirror of scg_params (defaults: the paper's, Section 7.1.2)."""
+    R: int = 10
+    T: int = 100
+    beta0: float = 1.0
+    K: float = math.inf
+    alpha: float = 0.0            # <= 0: sum(b)
+    seed: int = 0
+    q_mode: int = 0               # 0: ceil(t^(1/4) ln n); 1: fixed q_fixed
+    q_fixed: int = 0
+    scale: int = 1
+    trace_correct: int = 1
+    reorth: int = 0               # 0: paper's Lanczos; 2: full reorthogonalisation
+    precision: str = "fp64"       # "fp64" or "fp32"
+    instance: int = 0
+
+    def to_c(self) -> _lib.scg_params:
+        p = _lib.scg_params()
+        p.R, p.T, p.beta0, p.K, p.alpha = self.R, self.T, self.beta0, self.K, self.alpha
+        p.seed, p.q_mode, p.q_fixed, p.scale = self.seed, self.q_mode, self.q_fixed, self.scale
+        p.trace_correct, p.reorth, p.instance = self.trace_correct, self.reorth, self.instance
+        p.precision = {"fp64": _lib.SCG_FP64, "fp32": _lib.SCG_FP32_STREAM}[self.precision]
+        return p
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _dev(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dtype).contiguous()
+
+
+def workspace_bytes(params: Params, n: int, nnz: int) -> int:
+    lib = _lib.load()
+    out = C.c_size_t()
+    check(lib.scg_workspace_size(C.byref(params.to_c()), n, nnz, C.byref(out)), "scg_workspace_size")
+    return out.value
+
+
+class SketchyCGAL:
+    """One MaxCut SDP instance: C (CSR, symmetric, diagonal included), b.
+
+    Inputs may be numpy arrays or torch tensors; they are copied to `device`.
+    """
+
+    def __init__(self, row_ptr, col, val, b, params: Params, omega=None, device="cuda:0", stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.params = params
+        rp = _dev(row_ptr, torch.int64, self.device)
+        cl = _dev(col, torch.int32, self.device)
+        vl = _dev(val, torch.float64, self.device)
+        bb = _dev(b, torch.float64, self.device)
+        om = None if omega is None else _dev(omega, torch.float64, self.device)
+        self.n = int(bb.shape[0])
+        self.nnz = int(cl.shape[0])
+        if rp.shape[0] != self.n + 1 or vl.shape[0] != self.nnz:
+            raise ValueError("CSR arrays have inconsistent sizes")
+        if om is not None and om.numel() != self.n * params.R:
+            raise ValueError("omega must have n*R entries")
+        nbytes = workspace_bytes(params, self.n, self.nnz)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        cp = params.to_c()
+        st = self.lib.sketchycgal_init(C.byref(self.ctx), C.byref(cp), self.n, self.nnz, _ptr(rp), _ptr(cl),
+                                       _ptr(vl), _ptr(bb), _ptr(om), base + off, nbytes, self.stream.cuda_stream)
+        check(st, "sketchycgal_init")
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self.lib.sketchycgal_destroy(ctx)
+            self.ctx = None
+
+    def step(self, iters: int = 1):
+        check(self.lib.sketchycgal_step(self.ctx, iters), "sketchycgal_step")
+
+    def run(self, iters: int | None = None):
+        self.step(self.params.T if iters is None else iters)
+
+    def reconstruct(self):
+        R = self.params.R
+        U = torch.empty(R * self.n, dtype=torch.float64, device=self.device)
+        lam = torch.empty(R, dtype=torch.float64, device=self.device)
+        err = torch.empty(R, dtype=torch.float64, device=self.device)
+        check(self.lib.sketchycgal_reconstruct(self.ctx, _ptr(U), _ptr(lam), _ptr(err)), "sketchycgal_reconstruct")
+        return U.view(R, self.n).t(), lam, err
+
+    def log(self) -> dict:
+        cap = self.params.T
+        arr = (_lib.scg_iter_log * cap)()
+        cnt = C.c_int32()
+        check(self.lib.sketchycgal_log(self.ctx, arr, cap, C.byref(cnt)), "sketchycgal_log")
+        out = {}
+        for name, _ in _lib.scg_iter_log._fields_:
+            out[name] = np.array([getattr(arr[i], name) for i in range(cnt.value)])
+        return out
+
+    def summary(self, check_numeric: bool = True) -> dict:
+        s = _lib.scg_summary()
+        st = self.lib.sketchycgal_summary(self.ctx, C.byref(s))
+        if check_numeric:
+            check(st, "sketchycgal_summary")
+        return {name: getattr(s, name) for name, _ in _lib.scg_summary._fields_}
+
+    def get_state(self):
+        z = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        y = torch.empty_like(z)
+        S = torch.empty(self.n * self.params.R, dtype=torch.float64, device=self.device)
+        t = C.c_int32()
+        p = C.c_double()
+        tau = C.c_double()
+        check(self.lib.sketchycgal_get_state(self.ctx, C.byref(t), _ptr(z), _ptr(y), _ptr(S), C.byref(p),
+                                             C.byref(tau)), "sketchycgal_get_state")
+        return {"t": t.value, "z": z, "y": y, "S": S.view(self.n, self.params.R), "p": p.value, "tau": tau.value}
+
+    def set_state(self, t, z, y, S, p, tau):
+        z = _dev(z, torch.float64, self.device)
+        y = _dev(y, torch.float64, self.device)
+        S = _dev(S, torch.float64, self.device).reshape(-1)
+        check(self.lib.sketchycgal_set_state(self.ctx, int(t), _ptr(z), _ptr(y), _ptr(S), float(p), float(tau)),
+              "sketchycgal_set_state")
+
+    def lanczos_coeffs(self):
+        cap = 512
+        om = (C.c_double * cap)()
+        rh = (C.c_double * cap)()
+        k = C.c_int32()
+        xi = C.c_double()
+        check(self.lib.sketchycgal_lanczos_coeffs(self.ctx, om, rh, cap, C.byref(k), C.byref(xi)),
+              "sketchycgal_lanczos_coeffs")
+        kk = k.value
+        return np.array(om[:kk]), np.array(rh[:max(kk - 1, 0)]), xi.value
+
+    def apply(self, x):
+        x = _dev(x, torch.float64, self.device)
+        y = torch.empty_like(x)
+        check(self.lib.sketchycgal_apply(self.ctx, _ptr(x), _ptr(y)), "sketchycgal_apply")
+        return y
+
+    def time_spmv(self, reps: int = 50) -> float:
+        ms = C.c_double()
+        check(self.lib.sketchycgal_time_spmv(self.ctx, reps, C.byref(ms)), "sketchycgal_time_spmv")
+        return ms.value

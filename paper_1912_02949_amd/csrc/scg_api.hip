@@ -1,0 +1,678 @@
+// Host runtime and C ABI of the SketchyCGAL library (see include/sketchycgal.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "scg_kernels.hpp"
+
+using namespace scg;
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return SCG_EHIP;        \
+    } while (0)
+
+scg_status scg_reconstruct_impl(scg_ctx* c, double* U, double* lambda, double* err);
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int q_for(const scg_params& p, int64_t n, int t) {
+    int64_t q;
+    if (p.q_mode == 1) {
+        q = p.q_fixed;
+    } else {
+        q = (n > 1) ? (int64_t)std::ceil(std::pow((double)t, 0.25) * std::log((double)n)) : 1;
+    }
+    const int64_t cap = std::max<int64_t>(n - 1, 1);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(q, cap));
+}
+
+int qmax_for(const scg_params& p, int64_t n) {
+    int m = 1;
+    if (p.q_mode == 1) return q_for(p, n, 1);
+    return std::max(m, q_for(p, n, p.T));   // q_t is nondecreasing in t
+}
+
+size_t elem_size(const scg_params& p) { return p.precision == SCG_FP32_STREAM ? 4 : 8; }
+
+struct Layout {
+    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, total;
+    size_t recon_bytes;
+};
+
+Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
+    Layout L{};
+    const size_t es = elem_size(p);
+    const int qm = qmax_for(p, n);
+    const size_t R = (size_t)p.R;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.rp = take(sizeof(int32_t) * (n + 1));
+    L.col = take(sizeof(int32_t) * (size_t)nnz);
+    L.val = take(es * (size_t)nnz);
+    L.dC = take(8 * n);
+    L.b = take(8 * n);
+    L.z = take(8 * n);
+    L.y = take(8 * n);
+    L.s = take(es * n);
+    L.V = take(es * n * (size_t)(qm + 1));
+    L.u = take(es * n);
+    L.v = take(es * n);
+    L.Om = take(es * n * R);
+    L.S = take(es * n * R);
+    L.rb = take(sizeof(int32_t) * (n + 2));
+    L.sc = take(sizeof(DevScalars));
+    const size_t pw = 14 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
+    L.part = take(8 * (size_t)kGMax * pw);
+    L.counter = take(256);
+    L.logs = take(sizeof(scg_iter_log) * (size_t)p.T);
+    L.recon_bytes = 8 * (n * R + 256 * 3 * (size_t)kRMax * kRMax + 11 * (size_t)kRMax * kRMax + 64);
+    L.recon = take(L.recon_bytes);
+    L.total = off;
+    return L;
+}
+
+int round8(int64_t x) { return (int)((x + 7) / 8 * 8); }
+
+template <typename T>
+Prob<T> prob(scg_ctx* c) {
+    Prob<T> P;
+    P.n = c->n;
+    P.R = c->prm.R;
+    P.rp = c->rp;
+    P.col = c->col;
+    P.val = (const T*)c->val;
+    P.dC = c->dC;
+    P.b = c->b;
+    P.z = c->z;
+    P.y = c->y;
+    P.s = (T*)c->s;
+    P.V = (T*)c->V;
+    P.u = (T*)c->u;
+    P.v = (T*)c->v;
+    P.Om = (const T*)c->Om;
+    P.S = (T*)c->S;
+    P.rb = c->rb;
+    P.nrb = c->nrb;
+    P.sc = c->sc;
+    double* pp = c->part;
+    P.p_prep = pp;
+    P.p_spmv = pp + (size_t)kGMax * 6;
+    P.p_upd = pp + (size_t)kGMax * 7;
+    P.p_ritz = pp + (size_t)kGMax * 8;
+    P.p_obj = pp + (size_t)kGMax * (9 + kRMax);
+    P.p_primal = pp + (size_t)kGMax * (11 + kRMax);
+    P.p_h = pp + (size_t)kGMax * (14 + kRMax);
+    P.G = c->G;
+    P.Gs = c->Gs;
+    P.logs = c->logs;
+    P.T_iters = c->prm.T;
+    return P;
+}
+
+template <typename T, int MODE, int RB>
+void launch_spmv_rb(scg_ctx* c, const T* x, int step) {
+    Prob<T> P = prob<T>(c);
+    dim3 g(c->Gs), b(kBlock);
+    switch (c->lanes) {
+        case 1: hipLaunchKernelGGL((k_spmv<T, 1, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+        case 2: hipLaunchKernelGGL((k_spmv<T, 2, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+        case 4: hipLaunchKernelGGL((k_spmv<T, 4, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+        case 8: hipLaunchKernelGGL((k_spmv<T, 8, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+        case 16: hipLaunchKernelGGL((k_spmv<T, 16, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+        case 32: hipLaunchKernelGGL((k_spmv<T, 32, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+        default: hipLaunchKernelGGL((k_spmv<T, 64, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+    }
+}
+
+template <typename T, int MODE>
+void launch_spmv(scg_ctx* c, const T* x, int step) {
+    launch_spmv_rb<T, MODE, 8>(c, x, step);
+}
+
+template <typename T>
+void launch_ritz(scg_ctx* c) {
+    Prob<T> P = prob<T>(c);
+    dim3 g(c->G), b(kBlock), one(1);
+    const int R = c->prm.R;
+    if (R <= 8) {
+        hipLaunchKernelGGL((k_ritz<T, 8>), g, b, 0, c->stream, P);
+        hipLaunchKernelGGL((k_ritz_fin<8>), one, b, 0, c->stream, c->sc, P.p_ritz, c->G, R);
+    } else if (R <= 16) {
+        hipLaunchKernelGGL((k_ritz<T, 16>), g, b, 0, c->stream, P);
+        hipLaunchKernelGGL((k_ritz_fin<16>), one, b, 0, c->stream, c->sc, P.p_ritz, c->G, R);
+    } else {
+        hipLaunchKernelGGL((k_ritz<T, 32>), g, b, 0, c->stream, P);
+        hipLaunchKernelGGL((k_ritz_fin<32>), one, b, 0, c->stream, c->sc, P.p_ritz, c->G, R);
+    }
+}
+
+template <typename T>
+void launch_dual_sketch(scg_ctx* c, const IterArgs& it) {
+    Prob<T> P = prob<T>(c);
+    dim3 g(c->G), b(kBlock);
+    if (c->prm.R <= 8) hipLaunchKernelGGL((k_dual_sketch<T, 8>), g, b, 0, c->stream, P, it);
+    else if (c->prm.R <= 16) hipLaunchKernelGGL((k_dual_sketch<T, 16>), g, b, 0, c->stream, P, it);
+    else hipLaunchKernelGGL((k_dual_sketch<T, 32>), g, b, 0, c->stream, P, it);
+}
+
+IterArgs iter_args(scg_ctx* c, int t) {
+    IterArgs it;
+    it.t = t;
+    it.q = q_for(c->prm, c->n, t);
+    it.beta = c->prm.beta0 * std::sqrt(t + 1.0);
+    it.eta = 2.0 / (t + 1.0);
+    it.alpha = c->alpha_s;
+    it.beta0 = c->prm.beta0;
+    it.K = c->prm.K;
+    it.seed = c->prm.seed;
+    it.instance = (uint64_t)c->prm.instance;
+    return it;
+}
+
+template <typename T>
+void enqueue_prep(scg_ctx* c, const IterArgs& it) {
+    hipLaunchKernelGGL((k_prep<T>), dim3(c->G), dim3(kBlock), 0, c->stream, prob<T>(c), it);
+}
+
+template <typename T>
+void enqueue_iteration(scg_ctx* c, int t) {
+    const IterArgs it = iter_args(c, t);
+    Prob<T> P = prob<T>(c);
+    const T* V = (const T*)c->V;
+    const int64_t n = c->n;
+    enqueue_prep<T>(c, it);
+    for (int i = 0; i < it.q; ++i) {
+        launch_spmv<T, SPMV_LANCZOS>(c, V + (size_t)i * n, i);
+        if (i == it.q - 1) break;   // rho_q and v_{q+1} are never used
+        if (c->prm.reorth == 2) {
+            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 0);
+            hipLaunchKernelGGL((k_reorth_dot<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i);
+            hipLaunchKernelGGL(k_reduce_h, dim3(1), dim3(kBlock), 0, c->stream, c->sc, P.p_h, c->G, i);
+            hipLaunchKernelGGL((k_reorth_apply<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i);
+        } else {
+            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 1);
+        }
+    }
+    hipLaunchKernelGGL((k_tridiag<T>), dim3(1), dim3(64), 0, c->stream, P, it.q);
+    launch_ritz<T>(c);
+    launch_spmv<T, SPMV_OBJ>(c, (const T*)c->v, 0);
+    hipLaunchKernelGGL((k_primal<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, it);
+    launch_dual_sketch<T>(c, it);
+}
+
+// ------------------------------------------------------------- init kernels
+__global__ __launch_bounds__(kBlock) void k_validate(int64_t n, const int64_t* rp, const int32_t* col,
+                                                     const double* val, const double* b, int32_t* cnt,
+                                                     double* dCraw, DevScalars* sc, double* part,
+                                                     unsigned* counter) {
+    int64_t lo, hi;
+    split_range(n, xcd_lid(), gridDim.x, lo, hi);
+    double a[2] = {0.0, 0.0};
+    int err = 0;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+        int32_t c_off = 0;
+        double dsum = 0.0;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int32_t j = col[e];
+            const double v = val[e];
+            if (j < 0 || (int64_t)j >= n) err |= 1;
+            if (!isfinite(v)) err |= 2;
+            a[0] += v * v;
+            if ((int64_t)j == r) dsum += v;
+            else ++c_off;
+        }
+        cnt[r] = c_off;
+        dCraw[r] = dsum;
+        const double br = b[r];
+        if (!isfinite(br)) err |= 4;
+        a[1] += br;
+    }
+    if (err) atomicOr(&sc->err, err);
+    double tot[2];
+    if (grid_sum<2>(a, part, counter, tot) && threadIdx.x == 0) {
+        sc->sum_sq = tot[0];
+        sc->sum_b = tot[1];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const int64_t* rp, const int32_t* col,
+                                                    const double* val, const double* b_in, const int32_t* rp_off,
+                                                    int32_t* col_off, T* val_off, const double* dCraw, double* dC,
+                                                    double* b_out, double inv_cF, double inv_alpha) {
+    int64_t lo, hi;
+    split_range(n, xcd_lid(), gridDim.x, lo, hi);
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+        int32_t o = rp_off[r];
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int32_t j = col[e];
+            if ((int64_t)j == r) continue;
+            col_off[o] = j;
+            val_off[o] = (T)(val[e] * inv_cF);
+            ++o;
+        }
+        dC[r] = dCraw[r] * inv_cF;
+        b_out[r] = b_in[r] * inv_alpha;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_omega(int64_t n, int R, uint64_t seed, uint64_t instance, T* Om) {
+    const int64_t ng = (n + 3) / 4;
+    const int64_t total = ng * R;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t gi = i % ng;
+        const int c = (int)(i / ng);
+        double g[4];
+        normal4(seed, (uint64_t)gi, (uint64_t)c, instance, 1ull, g);
+        for (int m = 0; m < 4; ++m) {
+            const int64_t r = 4 * gi + m;
+            if (r < n) Om[(int64_t)c * n + r] = (T)g[m];
+        }
+    }
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_cast(int64_t cnt, const Tin* in, Tout* out) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * kBlock)
+        out[i] = (Tout)in[i];
+}
+
+// out (column-major n x R) <-> in (row-major n x R), with a type change.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_transpose_cast(int64_t n, int R, const Tin* in, Tout* out,
+                                                           int to_colmajor) {
+    const int64_t cnt = n * R;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * kBlock) {
+        if (to_colmajor) {
+            const int64_t r = i / R, c = i % R;           // i indexes the row-major input
+            out[c * n + r] = (Tout)in[i];
+        } else {
+            const int64_t c = i / n, r = i % n;           // i indexes the column-major input
+            out[r * R + c] = (Tout)in[i];
+        }
+    }
+}
+
+template <typename Tin, typename Tout>
+void transpose_cast(scg_ctx* c, const Tin* in, Tout* out, int to_colmajor) {
+    const int64_t cnt = c->n * c->prm.R;
+    const int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (cnt + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL((k_transpose_cast<Tin, Tout>), dim3(g), dim3(kBlock), 0, c->stream, c->n, c->prm.R, in, out,
+                       to_colmajor);
+}
+
+template <typename Tin, typename Tout>
+void cast(scg_ctx* c, int64_t cnt, const Tin* in, Tout* out) {
+    const int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (cnt + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(g), dim3(kBlock), 0, c->stream, cnt, in, out);
+}
+
+void partition_rows(const std::vector<int32_t>& rp, int64_t n, std::vector<int32_t>& rb) {
+    rb.clear();
+    rb.push_back(0);
+    int64_t cur_nnz = 0, cur_rows = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t len = rp[r + 1] - rp[r];
+        if (len > kNB) {
+            if (cur_rows > 0) rb.push_back((int32_t)r);
+            rb.push_back((int32_t)(r + 1));
+            cur_nnz = cur_rows = 0;
+            continue;
+        }
+        if (cur_rows > 0 && (cur_nnz + len > kNB || cur_rows >= kRowsCap)) {
+            rb.push_back((int32_t)r);
+            cur_nnz = cur_rows = 0;
+        }
+        cur_nnz += len;
+        ++cur_rows;
+    }
+    if (cur_rows > 0) rb.push_back((int32_t)n);
+}
+
+int pick_lanes(double mean_len) {
+    int l = 1;
+    while (l < 32 && 2.0 * l <= mean_len) l *= 2;
+    return l;
+}
+
+template <typename T>
+scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, const double* val, const double* b,
+                      const double* omega) {
+    const int64_t n = c->n;
+    std::vector<int64_t> hrp(n + 1);
+    HIP_TRY(hipMemcpyAsync(hrp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (hrp[0] != 0 || hrp[n] != c->nnz_in) return SCG_EINVAL;
+    for (int64_t r = 0; r < n; ++r)
+        if (hrp[r + 1] < hrp[r]) return SCG_EINVAL;
+    int32_t* cnt = c->rb;   // n ints of scratch before the partition is written
+    double* dCraw = c->z;   // scratch before the state is zeroed
+    HIP_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
+    HIP_TRY(hipMemsetAsync(c->counter, 0, 256, c->stream));
+    hipLaunchKernelGGL(k_validate, dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, cnt, dCraw,
+                       c->sc, c->part, c->counter);
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> hcnt(n);
+    HIP_TRY(hipMemcpyAsync(hcnt.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    DevScalars hsc;
+    HIP_TRY(hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (hsc.err != 0) return SCG_EINVAL;
+    const double alpha = (c->prm.alpha > 0.0) ? c->prm.alpha : hsc.sum_b;
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return SCG_EINVAL;
+    c->alpha_orig = alpha;
+    double cF = std::sqrt(hsc.sum_sq);
+    if (!(cF > 0.0)) cF = 1.0;
+    c->c_F = c->prm.scale ? cF : 1.0;
+    c->alpha_s = c->prm.scale ? 1.0 : alpha;
+    std::vector<int32_t> hrp_off(n + 1);
+    int64_t acc = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        hrp_off[r] = (int32_t)acc;
+        acc += hcnt[r];
+        if (acc > INT32_MAX) return SCG_EINVAL;
+    }
+    hrp_off[n] = (int32_t)acc;
+    c->nnz_off = acc;
+    std::vector<int32_t> hrb;
+    partition_rows(hrp_off, n, hrb);
+    c->nrb = (int)hrb.size() - 1;
+    c->Gs = std::min(kGMax, std::max(8, round8(c->nrb)));
+    c->lanes = pick_lanes(n > 0 ? (double)acc / (double)n : 1.0);
+    HIP_TRY(hipMemcpyAsync(c->rp, hrp_off.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->rb, hrb.data(), sizeof(int32_t) * hrb.size(), hipMemcpyHostToDevice, c->stream));
+    const double inv_cF = 1.0 / c->c_F;
+    const double inv_alpha = c->prm.scale ? 1.0 / alpha : 1.0;
+    hipLaunchKernelGGL((k_scatter<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, c->rp,
+                       c->col, (T*)c->val, dCraw, c->dC, c->b, inv_cF, inv_alpha);
+    HIP_TRY(hipGetLastError());
+    if (omega) {
+        transpose_cast<double, T>(c, omega, (T*)c->Om, 1);
+    } else {
+        const int64_t total = (n + 3) / 4 * c->prm.R;
+        const int g = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (total + kBlock - 1) / kBlock));
+        hipLaunchKernelGGL((k_omega<T>), dim3(g), dim3(kBlock), 0, c->stream, n, c->prm.R, c->prm.seed,
+                           (uint64_t)c->prm.instance, (T*)c->Om);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));   // dCraw (in z) is consumed before z is zeroed
+    HIP_TRY(hipMemsetAsync(c->z, 0, 8 * n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->y, 0, 8 * n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->S, 0, elem_size(c->prm) * n * c->prm.R, c->stream));
+    HIP_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
+    HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * c->prm.T, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->t_next = 1;
+    return SCG_OK;
+}
+
+bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
+    if (!p || n < 1 || nnz < 0 || n >= INT32_MAX) return false;
+    if (p->R < 1 || p->R > kRMax || p->R > n) return false;
+    if (p->T < 1) return false;
+    if (!(p->beta0 > 0.0) || !(p->K >= 0.0)) return false;
+    if (p->q_mode != 0 && p->q_mode != 1) return false;
+    if (p->q_mode == 1 && p->q_fixed < 1) return false;
+    if (p->reorth != 0 && p->reorth != 2) return false;
+    if (p->precision != SCG_FP64 && p->precision != SCG_FP32_STREAM) return false;
+    if (qmax_for(*p, n) + 1 > kQCap) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void scg_default_params(scg_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->R = 10;
+    p->T = 100;
+    p->beta0 = 1.0;
+    p->K = INFINITY;
+    p->alpha = 0.0;
+    p->seed = 0;
+    p->q_mode = 0;
+    p->q_fixed = 0;
+    p->scale = 1;
+    p->trace_correct = 1;
+    p->reorth = 0;
+    p->precision = SCG_FP64;
+    p->instance = 0;
+}
+
+scg_status scg_workspace_size(const scg_params* p, int64_t n, int64_t nnz, size_t* bytes) {
+    if (!bytes || !params_ok(p, n, nnz)) return SCG_EINVAL;
+    *bytes = make_layout(*p, n, nnz).total;
+    return SCG_OK;
+}
+
+scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col, const double* val, const double* b, const double* omega,
+                            void* workspace, size_t ws_bytes, void* stream) {
+    if (!out) return SCG_EINVAL;
+    *out = nullptr;
+    if (!params_ok(p, n, nnz) || !row_ptr || !b || !workspace) return SCG_EINVAL;
+    if (nnz > 0 && (!col || !val)) return SCG_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return SCG_EINVAL;
+    const Layout L = make_layout(*p, n, nnz);
+    if (ws_bytes < L.total) return SCG_ENOMEM;
+    scg_ctx* c = new (std::nothrow) scg_ctx();
+    if (!c) return SCG_ENOMEM;
+    c->prm = *p;
+    c->n = n;
+    c->nnz_in = nnz;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return SCG_EHIP; }
+    c->qmax = qmax_for(*p, n);
+    c->G = std::min(kGMax, std::max(8, round8((n + 1023) / 1024)));
+    char* base = (char*)workspace;
+    c->rp = (int32_t*)(base + L.rp);
+    c->col = (int32_t*)(base + L.col);
+    c->val = base + L.val;
+    c->dC = (double*)(base + L.dC);
+    c->b = (double*)(base + L.b);
+    c->z = (double*)(base + L.z);
+    c->y = (double*)(base + L.y);
+    c->s = base + L.s;
+    c->V = base + L.V;
+    c->u = base + L.u;
+    c->v = base + L.v;
+    c->Om = base + L.Om;
+    c->S = base + L.S;
+    c->rb = (int32_t*)(base + L.rb);
+    c->sc = (DevScalars*)(base + L.sc);
+    c->part = (double*)(base + L.part);
+    c->counter = (unsigned*)(base + L.counter);
+    c->logs = (scg_iter_log*)(base + L.logs);
+    c->recon = (double*)(base + L.recon);
+    c->recon_bytes = L.recon_bytes;
+    scg_status st = (p->precision == SCG_FP32_STREAM) ? init_typed<float>(c, row_ptr, col, val, b, omega)
+                                                       : init_typed<double>(c, row_ptr, col, val, b, omega);
+    if (st != SCG_OK) {
+        (void)hipStreamSynchronize(c->stream);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return SCG_OK;
+}
+
+scg_status sketchycgal_step(scg_ctx* c, int32_t iters) {
+    if (!c || iters < 0) return SCG_EINVAL;
+    if ((int64_t)c->t_next - 1 + iters > c->prm.T) return SCG_ESTATE;
+    for (int k = 0; k < iters; ++k) {
+        if (c->prm.precision == SCG_FP32_STREAM) enqueue_iteration<float>(c, c->t_next);
+        else enqueue_iteration<double>(c, c->t_next);
+        c->t_next++;
+    }
+    HIP_TRY(hipGetLastError());
+    return SCG_OK;
+}
+
+scg_status sketchycgal_log(scg_ctx* c, scg_iter_log* host_out, int32_t max, int32_t* count) {
+    if (!c || !host_out || !count || max < 0) return SCG_EINVAL;
+    const int done = c->t_next - 1;
+    const int m = std::min(done, (int)max);
+    if (m > 0) HIP_TRY(hipMemcpyAsync(host_out, c->logs, sizeof(scg_iter_log) * m, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *count = m;
+    return SCG_OK;
+}
+
+scg_status sketchycgal_summary(scg_ctx* c, scg_summary* o) {
+    if (!c || !o) return SCG_EINVAL;
+    DevScalars hsc;
+    HIP_TRY(hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // ||z - b|| after the last update: recomputed from the log of the last iteration
+    double infeas_s = 0.0;
+    const int done = c->t_next - 1;
+    if (done > 0) {
+        scg_iter_log L;
+        HIP_TRY(hipMemcpy(&L, c->logs + (done - 1), sizeof(L), hipMemcpyDeviceToHost));
+        infeas_s = L.infeas;
+    }
+    o->t_done = done;
+    o->status_flags = (hsc.flags & 2) ? 1 : 0;
+    o->p_scaled = hsc.p;
+    o->tau_scaled = hsc.tau;
+    o->c_F = c->c_F;
+    o->alpha = c->alpha_orig;
+    o->alpha_scaled = c->alpha_s;
+    o->objective = c->c_F * c->alpha_orig * hsc.p / c->alpha_s;
+    o->infeasibility = c->alpha_orig / c->alpha_s * infeas_s;
+    return (hsc.flags & 2) ? SCG_ENUMERIC : SCG_OK;
+}
+
+scg_status sketchycgal_get_state(scg_ctx* c, int32_t* t_next, double* z, double* y, double* S, double* p,
+                                 double* tau) {
+    if (!c) return SCG_EINVAL;
+    const int64_t n = c->n;
+    if (z) HIP_TRY(hipMemcpyAsync(z, c->z, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+    if (y) HIP_TRY(hipMemcpyAsync(y, c->y, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+    if (S) {
+        if (c->prm.precision == SCG_FP32_STREAM) transpose_cast<float, double>(c, (const float*)c->S, S, 0);
+        else transpose_cast<double, double>(c, (const double*)c->S, S, 0);
+    }
+    DevScalars hsc;
+    HIP_TRY(hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (t_next) *t_next = c->t_next;
+    if (p) *p = hsc.p;
+    if (tau) *tau = hsc.tau;
+    return SCG_OK;
+}
+
+scg_status sketchycgal_set_state(scg_ctx* c, int32_t t_next, const double* z, const double* y, const double* S,
+                                 double p, double tau) {
+    if (!c || t_next < 1 || t_next > c->prm.T + 1 || !z || !y || !S) return SCG_EINVAL;
+    const int64_t n = c->n;
+    HIP_TRY(hipMemcpyAsync(c->z, z, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->y, y, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+    if (c->prm.precision == SCG_FP32_STREAM) transpose_cast<double, float>(c, S, (float*)c->S, 1);
+    else transpose_cast<double, double>(c, S, (double*)c->S, 1);
+    DevScalars hsc;
+    HIP_TRY(hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    hsc.p = p;
+    hsc.tau = tau;
+    HIP_TRY(hipMemcpyAsync(c->sc, &hsc, sizeof(DevScalars), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->t_next = t_next;
+    return SCG_OK;
+}
+
+scg_status sketchycgal_lanczos_coeffs(scg_ctx* c, double* omega, double* rho, int32_t cap, int32_t* k, double* xi) {
+    if (!c || !k) return SCG_EINVAL;
+    DevScalars hsc;
+    HIP_TRY(hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *k = hsc.k;
+    if (xi) *xi = hsc.xi;
+    for (int i = 0; i < std::min<int>(hsc.k, cap); ++i) {
+        if (omega) omega[i] = hsc.omega[i];
+        if (rho && i < hsc.k - 1) rho[i] = hsc.rho[i];
+    }
+    return SCG_OK;
+}
+
+scg_status sketchycgal_apply(scg_ctx* c, const double* x, double* y) {
+    if (!c || !x || !y) return SCG_EINVAL;
+    if (c->t_next > c->prm.T) return SCG_ESTATE;
+    const IterArgs it = iter_args(c, c->t_next);
+    const int64_t n = c->n;
+    if (c->prm.precision == SCG_FP32_STREAM) {
+        enqueue_prep<float>(c, it);
+        float* xs = (float*)c->V + n;
+        cast<double, float>(c, n, x, xs);
+        launch_spmv<float, SPMV_APPLY>(c, xs, 0);
+        cast<float, double>(c, n, (const float*)c->u, y);
+    } else {
+        enqueue_prep<double>(c, it);
+        launch_spmv<double, SPMV_APPLY>(c, x, 0);
+        HIP_TRY(hipMemcpyAsync(y, c->u, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCG_OK;
+}
+
+scg_status sketchycgal_time_spmv(scg_ctx* c, int32_t reps, double* avg_ms) {
+    if (!c || reps < 1 || !avg_ms) return SCG_EINVAL;
+    if (c->t_next > c->prm.T) return SCG_ESTATE;
+    const IterArgs it = iter_args(c, c->t_next);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    if (c->prm.precision == SCG_FP32_STREAM) enqueue_prep<float>(c, it);
+    else enqueue_prep<double>(c, it);
+    HIP_TRY(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) {
+        if (c->prm.precision == SCG_FP32_STREAM) launch_spmv<float, SPMV_LANCZOS>(c, (const float*)c->V, 0);
+        else launch_spmv<double, SPMV_LANCZOS>(c, (const double*)c->V, 0);
+    }
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
+    return SCG_OK;
+}
+
+scg_status sketchycgal_reconstruct(scg_ctx* c, double* U, double* lambda, double* err) {
+    if (!c || !U || !lambda) return SCG_EINVAL;
+    return scg_reconstruct_impl(c, U, lambda, err);
+}
+
+void sketchycgal_destroy(scg_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+const char* scg_status_string(scg_status s) {
+    switch (s) {
+        case SCG_OK: return "ok";
+        case SCG_EINVAL: return "invalid argument";
+        case SCG_ENOMEM: return "workspace too small";
+        case SCG_EHIP: return "HIP runtime error";
+        case SCG_ENUMERIC: return "numerical failure (NaN/Inf or Cholesky)";
+        case SCG_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

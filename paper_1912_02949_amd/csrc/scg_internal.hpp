@@ -1,0 +1,109 @@
+// Internal layout shared by the SketchyCGAL host runtime and its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sketchycgal.h"
+
+namespace scg {
+
+constexpr int kQCap = 512;     // maximum Lanczos steps per call
+constexpr int kRMax = 32;      // maximum sketch size R
+constexpr int kNB = 2048;      // nonzeros staged through LDS per row block
+constexpr int kRowsCap = 512;  // rows per row block
+constexpr int kGMax = 2048;    // workgroups of a streaming launch
+
+// Scalars of the current iteration, resident in device memory.  Indexing of
+// the Lanczos run: basis vector V[j] (j = 0 .. k-1) is stored unnormalised;
+// inv[j] is the factor that normalises it.  omega[j] = v_j^T M v_j,
+// rho[j] = norm of the vector that becomes V[j+1].
+struct DevScalars {
+    double omega[kQCap];
+    double rho[kQCap];
+    double inv[kQCap + 1];
+    double coef[kQCap];       // Ritz coefficients u_j * inv[j]
+    double h[kQCap];          // reorthogonalisation coefficients
+    double comega[kRMax];     // v^T Omega for the normalised Ritz vector
+    double xi, vnorm2, inv_vnorm, cv, resid2;
+    double p, tau, gamma_eff;
+    double d_yb, d_zz, d_gapdot, d_zb2, b2;   // state before the update
+    double sum_sq, sum_b;                      // init: sum C_ij^2, sum b
+    double c_F, alpha_s;
+    int32_t k, done, flags, t_done;
+    int32_t err;                               // init validation bits
+    int32_t pad;
+};
+
+// Problem description passed by value to kernels.
+template <typename T>
+struct Prob {
+    int64_t n;
+    int R;
+    const int32_t* rp;    // off-diagonal CSR, int32[n+1]
+    const int32_t* col;
+    const T* val;
+    const double* dC;     // diagonal of C (scaled)
+    const double* b;      // scaled b
+    double* z;
+    double* y;
+    T* s;                 // diagonal shift of D: dC + y + beta (z - b)
+    T* V;                 // Lanczos basis, (qmax+1) columns of n
+    T* u;                 // SpMV output
+    T* v;                 // Ritz vector (unnormalised)
+    const T* Om;          // Omega, n x R column-major (column c at c*n)
+    T* S;                 // sketch, n x R column-major
+    const int32_t* rb;    // row-block boundaries, int32[nrb+1]
+    int nrb;
+    DevScalars* sc;
+    // per-workgroup partial sums, one buffer per producing kernel
+    double* p_prep;       // k_prep,        G  x 6
+    double* p_spmv;       // k_spmv LANCZOS, Gs x 1
+    double* p_upd;        // k_lupdate / k_reorth_apply, G x 1
+    double* p_ritz;       // k_ritz,        G  x (RB + 1)
+    double* p_obj;        // k_spmv OBJ,    Gs x 2
+    double* p_primal;     // k_primal,      G  x 3
+    double* p_h;          // k_reorth_dot,  G  x (step + 1)
+    int G;                // workgroups of the vector kernels
+    int Gs;               // workgroups of the SpMV kernels
+    scg_iter_log* logs;
+    int T_iters;
+};
+
+}  // namespace scg
+
+struct scg_ctx {
+    scg_params prm;
+    int64_t n, nnz_in, nnz_off;
+    hipStream_t stream;
+    int device;
+    int t_next;
+    int qmax;
+    int G;          // workgroups for vector kernels
+    int Gs;         // workgroups for SpMV kernels
+    int lanes;      // lanes per row in the SpMV row reduction
+    int nrb;
+    double alpha_orig;
+    double c_F;
+    double alpha_s;
+    // device memory carved from the workspace
+    int32_t* rp;
+    int32_t* col;
+    void* val;
+    double* dC;
+    double* b;
+    double* z;
+    double* y;
+    void* s;
+    void* V;
+    void* u;
+    void* v;
+    void* Om;
+    void* S;
+    int32_t* rb;
+    scg::DevScalars* sc;
+    double* part;       // partial sums (iteration kernels use fixed slices of it)
+    unsigned* counter;  // last-workgroup ticket (initialisation and reconstruction)
+    scg_iter_log* logs;
+    double* recon;   // reconstruction scratch (n x R FP64 and small matrices)
+    size_t recon_bytes;
+};

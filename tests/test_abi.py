@@ -1,0 +1,76 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/sketchycgal.h, and rejects bad parameters before any
+device work."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_1912_02949_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sketchycgal.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:scg|sketchycgal)_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib.load()
+    names = _declared()
+    assert "sketchycgal_init" in names and "sketchycgal_step" in names and "sketchycgal_reconstruct" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_default_params_are_the_papers():
+    lib = _lib.load()
+    p = _lib.scg_params()
+    lib.scg_default_params(C.byref(p))
+    assert p.beta0 == 1.0 and math.isinf(p.K) and p.scale == 1 and p.trace_correct == 1
+    assert p.q_mode == 0 and p.reorth == 0 and p.precision == _lib.SCG_FP64
+
+
+def _ws(**kw):
+    lib = _lib.load()
+    p = _lib.scg_params()
+    lib.scg_default_params(C.byref(p))
+    n = kw.pop("n", 100)
+    nnz = kw.pop("nnz", 500)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    out = C.c_size_t()
+    return lib.scg_workspace_size(C.byref(p), n, nnz, C.byref(out)), out.value
+
+
+def test_workspace_size_and_validation():
+    st, b = _ws()
+    assert st == _lib.SCG_OK and b > 0
+    st2, b2 = _ws(precision=_lib.SCG_FP32_STREAM)
+    assert st2 == _lib.SCG_OK and b2 < b
+    bad = [dict(R=0), dict(R=33), dict(n=5, R=6), dict(T=0), dict(beta0=0.0), dict(beta0=-1.0), dict(K=-1.0),
+           dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=1), dict(precision=7), dict(n=0),
+           dict(q_mode=1, q_fixed=600, n=10_000)]
+    for kw in bad:
+        st, _ = _ws(**dict(kw))
+        assert st == _lib.SCG_EINVAL, kw
+
+
+def test_init_rejects_null_and_misaligned_arguments():
+    lib = _lib.load()
+    p = _lib.scg_params()
+    lib.scg_default_params(C.byref(p))
+    ctx = C.c_void_p()
+    # NULL arrays and a misaligned workspace are rejected before any HIP call
+    assert lib.sketchycgal_init(C.byref(ctx), C.byref(p), 10, 20, None, None, None, None, None, None, 0,
+                                None) == _lib.SCG_EINVAL
+    assert lib.sketchycgal_init(C.byref(ctx), C.byref(p), 10, 20, 8, 8, 8, 8, None, 12345, 1 << 30,
+                                None) == _lib.SCG_EINVAL
+    assert ctx.value is None
+    assert lib.sketchycgal_step(None, 1) == _lib.SCG_EINVAL
+    assert lib.scg_status_string(_lib.SCG_ENOMEM) == b"workspace too small"
