@@ -69,6 +69,9 @@ typedef struct {
     int32_t  reorth;        /* 0: Lanczos as in alg:rand-lanczos; 2: full reorthogonalisation */
     int32_t  precision;     /* scg_precision                                                 */
     int32_t  instance;      /* Philox counter word selecting this problem's random streams   */
+    int32_t  matrix_format; /* 0: compress the off-diagonal values when they share one
+                               magnitude (columns only, sign in bit 31); 1: always store values */
+    int32_t  autotune;      /* 1: time the SpMV row-reduction variants at init, keep the fastest */
 } scg_params;
 
 /* One record per iteration t, in scaled units (see file comment).  Gap and

@@ -16,7 +16,8 @@ class scg_params(C.Structure):
         ("R", C.c_int32), ("T", C.c_int32), ("beta0", C.c_double), ("K", C.c_double),
         ("alpha", C.c_double), ("seed", C.c_uint64), ("q_mode", C.c_int32), ("q_fixed", C.c_int32),
         ("scale", C.c_int32), ("trace_correct", C.c_int32), ("reorth", C.c_int32),
-        ("precision", C.c_int32), ("instance", C.c_int32),
+        ("precision", C.c_int32), ("instance", C.c_int32), ("matrix_format", C.c_int32),
+        ("autotune", C.c_int32),
     ]
 
 

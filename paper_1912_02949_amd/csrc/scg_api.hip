@@ -53,6 +53,7 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     const size_t es = elem_size(p);
     const int qm = qmax_for(p, n);
     const size_t R = (size_t)p.R;
+    const size_t ld = (size_t)((n + 63) / 64 * 64);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.rp = take(sizeof(int32_t) * (n + 1));
@@ -63,11 +64,11 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.z = take(8 * n);
     L.y = take(8 * n);
     L.s = take(es * n);
-    L.V = take(es * n * (size_t)(qm + 1));
+    L.V = take(es * ld * (size_t)(qm + 1));
     L.u = take(es * n);
     L.v = take(es * n);
-    L.Om = take(es * n * R);
-    L.S = take(es * n * R);
+    L.Om = take(es * ld * R);
+    L.S = take(es * ld * R);
     L.rb = take(sizeof(int32_t) * (n + 2));
     L.sc = take(sizeof(DevScalars));
     const size_t pw = 14 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
@@ -86,10 +87,12 @@ template <typename T>
 Prob<T> prob(scg_ctx* c) {
     Prob<T> P;
     P.n = c->n;
+    P.ld = c->ld;
     P.R = c->prm.R;
     P.rp = c->rp;
     P.col = c->col;
     P.val = (const T*)c->val;
+    P.cval = c->cval;
     P.dC = c->dC;
     P.b = c->b;
     P.z = c->z;
@@ -118,24 +121,25 @@ Prob<T> prob(scg_ctx* c) {
     return P;
 }
 
-template <typename T, int MODE, int RB>
-void launch_spmv_rb(scg_ctx* c, const T* x, int step) {
+template <typename T, int MODE, int RB, int FMT>
+void launch_spmv_f(scg_ctx* c, const T* x, int step, int lanes) {
     Prob<T> P = prob<T>(c);
     dim3 g(c->Gs), b(kBlock);
-    switch (c->lanes) {
-        case 1: hipLaunchKernelGGL((k_spmv<T, 1, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
-        case 2: hipLaunchKernelGGL((k_spmv<T, 2, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
-        case 4: hipLaunchKernelGGL((k_spmv<T, 4, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
-        case 8: hipLaunchKernelGGL((k_spmv<T, 8, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
-        case 16: hipLaunchKernelGGL((k_spmv<T, 16, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
-        case 32: hipLaunchKernelGGL((k_spmv<T, 32, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
-        default: hipLaunchKernelGGL((k_spmv<T, 64, MODE, RB>), g, b, 0, c->stream, P, x, step); break;
+    switch (lanes) {
+        case 2: hipLaunchKernelGGL((k_spmv<T, 2, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
+        case 4: hipLaunchKernelGGL((k_spmv<T, 4, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
+        case 8: hipLaunchKernelGGL((k_spmv<T, 8, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
+        case 16: hipLaunchKernelGGL((k_spmv<T, 16, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
+        default: hipLaunchKernelGGL((k_spmv<T, 32, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
     }
 }
 
 template <typename T, int MODE>
-void launch_spmv(scg_ctx* c, const T* x, int step) {
-    launch_spmv_rb<T, MODE, 8>(c, x, step);
+void launch_spmv(scg_ctx* c, const T* x, int step, int lanes = 0) {
+    if (lanes == 0) lanes = c->lanes;
+    if (c->fmt == FMT_PAT) launch_spmv_f<T, MODE, 8, FMT_PAT>(c, x, step, lanes);
+    else if (c->fmt == FMT_SGN) launch_spmv_f<T, MODE, 8, FMT_SGN>(c, x, step, lanes);
+    else launch_spmv_f<T, MODE, 8, FMT_VAL>(c, x, step, lanes);
 }
 
 template <typename T>
@@ -188,10 +192,9 @@ void enqueue_iteration(scg_ctx* c, int t) {
     const IterArgs it = iter_args(c, t);
     Prob<T> P = prob<T>(c);
     const T* V = (const T*)c->V;
-    const int64_t n = c->n;
     enqueue_prep<T>(c, it);
     for (int i = 0; i < it.q; ++i) {
-        launch_spmv<T, SPMV_LANCZOS>(c, V + (size_t)i * n, i);
+        launch_spmv<T, SPMV_LANCZOS>(c, V + (size_t)i * c->ld, i);
         if (i == it.q - 1) break;   // rho_q and v_{q+1} are never used
         if (c->prm.reorth == 2) {
             hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 0);
@@ -202,7 +205,7 @@ void enqueue_iteration(scg_ctx* c, int t) {
             hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 1);
         }
     }
-    hipLaunchKernelGGL((k_tridiag<T>), dim3(1), dim3(64), 0, c->stream, P, it.q);
+    hipLaunchKernelGGL((k_tridiag<T>), dim3(1), dim3(kBlock), 0, c->stream, P, it.q);
     launch_ritz<T>(c);
     launch_spmv<T, SPMV_OBJ>(c, (const T*)c->v, 0);
     hipLaunchKernelGGL((k_primal<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, it);
@@ -213,10 +216,11 @@ void enqueue_iteration(scg_ctx* c, int t) {
 __global__ __launch_bounds__(kBlock) void k_validate(int64_t n, const int64_t* rp, const int32_t* col,
                                                      const double* val, const double* b, int32_t* cnt,
                                                      double* dCraw, DevScalars* sc, double* part,
-                                                     unsigned* counter) {
+                                                     unsigned* counter, double* mm) {
     int64_t lo, hi;
     split_range(n, xcd_lid(), gridDim.x, lo, hi);
     double a[2] = {0.0, 0.0};
+    double vmin = INFINITY, vmax = -INFINITY, amin = INFINITY, amax = -INFINITY;
     int err = 0;
     for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
         int32_t c_off = 0;
@@ -227,8 +231,15 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n, const int64_t* r
             if (j < 0 || (int64_t)j >= n) err |= 1;
             if (!isfinite(v)) err |= 2;
             a[0] += v * v;
-            if ((int64_t)j == r) dsum += v;
-            else ++c_off;
+            if ((int64_t)j == r) {
+                dsum += v;
+            } else {
+                ++c_off;
+                vmin = fmin(vmin, v);
+                vmax = fmax(vmax, v);
+                amin = fmin(amin, fabs(v));
+                amax = fmax(amax, fabs(v));
+            }
         }
         cnt[r] = c_off;
         dCraw[r] = dsum;
@@ -237,6 +248,22 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n, const int64_t* r
         a[1] += br;
     }
     if (err) atomicOr(&sc->err, err);
+    // per-workgroup extremes of the off-diagonal values (combined on the host)
+    {
+        __shared__ double red4[4][kWaves];
+        double m4[4] = {vmin, -vmax, amin, -amax};
+        for (int i = 0; i < 4; ++i) {
+            double v = m4[i];
+            for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+            if ((threadIdx.x & 63) == 0) red4[i][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double v = red4[threadIdx.x][0];
+            for (int w = 1; w < kWaves; ++w) v = fmin(v, red4[threadIdx.x][w]);
+            mm[(size_t)blockIdx.x * 4 + threadIdx.x] = v;
+        }
+    }
     double tot[2];
     if (grid_sum<2>(a, part, counter, tot) && threadIdx.x == 0) {
         sc->sum_sq = tot[0];
@@ -248,7 +275,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const int64_t* rp, const int32_t* col,
                                                     const double* val, const double* b_in, const int32_t* rp_off,
                                                     int32_t* col_off, T* val_off, const double* dCraw, double* dC,
-                                                    double* b_out, double inv_cF, double inv_alpha) {
+                                                    double* b_out, double inv_cF, double inv_alpha, int fmt) {
     int64_t lo, hi;
     split_range(n, xcd_lid(), gridDim.x, lo, hi);
     for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
@@ -256,8 +283,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const int64_t* rp
         for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
             const int32_t j = col[e];
             if ((int64_t)j == r) continue;
-            col_off[o] = j;
-            val_off[o] = (T)(val[e] * inv_cF);
+            if (fmt == FMT_VAL) {
+                col_off[o] = j;
+                val_off[o] = (T)(val[e] * inv_cF);
+            } else if (fmt == FMT_PAT) {
+                col_off[o] = j;
+            } else {
+                col_off[o] = (val[e] < 0.0) ? (int32_t)((uint32_t)j | 0x80000000u) : j;
+            }
             ++o;
         }
         dC[r] = dCraw[r] * inv_cF;
@@ -266,7 +299,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const int64_t* rp
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_omega(int64_t n, int R, uint64_t seed, uint64_t instance, T* Om) {
+__global__ __launch_bounds__(kBlock) void k_omega(int64_t n, int64_t ld, int R, uint64_t seed, uint64_t instance,
+                                                  T* Om) {
     const int64_t ng = (n + 3) / 4;
     const int64_t total = ng * R;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
@@ -276,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_omega(int64_t n, int R, uint64_t see
         normal4(seed, (uint64_t)gi, (uint64_t)c, instance, 1ull, g);
         for (int m = 0; m < 4; ++m) {
             const int64_t r = 4 * gi + m;
-            if (r < n) Om[(int64_t)c * n + r] = (T)g[m];
+            if (r < n) Om[(int64_t)c * ld + r] = (T)g[m];
         }
     }
 }
@@ -289,16 +323,16 @@ __global__ __launch_bounds__(kBlock) void k_cast(int64_t cnt, const Tin* in, Tou
 
 // out (column-major n x R) <-> in (row-major n x R), with a type change.
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kBlock) void k_transpose_cast(int64_t n, int R, const Tin* in, Tout* out,
+__global__ __launch_bounds__(kBlock) void k_transpose_cast(int64_t n, int64_t ld, int R, const Tin* in, Tout* out,
                                                            int to_colmajor) {
     const int64_t cnt = n * R;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * kBlock) {
         if (to_colmajor) {
             const int64_t r = i / R, c = i % R;           // i indexes the row-major input
-            out[c * n + r] = (Tout)in[i];
+            out[c * ld + r] = (Tout)in[i];
         } else {
-            const int64_t c = i / n, r = i % n;           // i indexes the column-major input
-            out[r * R + c] = (Tout)in[i];
+            const int64_t c = i / n, r = i % n;           // i indexes column c, row r
+            out[r * R + c] = (Tout)in[c * ld + r];
         }
     }
 }
@@ -307,8 +341,8 @@ template <typename Tin, typename Tout>
 void transpose_cast(scg_ctx* c, const Tin* in, Tout* out, int to_colmajor) {
     const int64_t cnt = c->n * c->prm.R;
     const int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (cnt + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL((k_transpose_cast<Tin, Tout>), dim3(g), dim3(kBlock), 0, c->stream, c->n, c->prm.R, in, out,
-                       to_colmajor);
+    hipLaunchKernelGGL((k_transpose_cast<Tin, Tout>), dim3(g), dim3(kBlock), 0, c->stream, c->n, c->ld, c->prm.R,
+                       in, out, to_colmajor);
 }
 
 template <typename Tin, typename Tout>
@@ -340,9 +374,39 @@ void partition_rows(const std::vector<int32_t>& rp, int64_t n, std::vector<int32
 }
 
 int pick_lanes(double mean_len) {
-    int l = 1;
+    int l = 2;
     while (l < 32 && 2.0 * l <= mean_len) l *= 2;
     return l;
+}
+
+// Autotuner: time the Lanczos SpMV for each lanes-per-row choice on this
+// matrix (after a k_prep of iteration 1 has filled the start vector and the
+// shift) and keep the fastest.  Timed with HIP events on the context stream.
+template <typename T>
+scg_status autotune_lanes(scg_ctx* c) {
+    const IterArgs it = iter_args(c, 1);
+    enqueue_prep<T>(c, it);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const double mean = c->n > 0 ? (double)c->nnz_off / (double)c->n : 1.0;
+    float best = 1e30f;
+    int best_l = c->lanes;
+    for (int l : {2, 4, 8, 16, 32}) {
+        if (l > 4 * mean + 4) break;
+        launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);   // warm-up
+        HIP_TRY(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);
+        HIP_TRY(hipEventRecord(e1, c->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; best_l = l; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->lanes = best_l;
+    return SCG_OK;
 }
 
 template <typename T>
@@ -359,11 +423,14 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     double* dCraw = c->z;   // scratch before the state is zeroed
     HIP_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
     HIP_TRY(hipMemsetAsync(c->counter, 0, 256, c->stream));
+    double* mm = c->part + (size_t)kGMax * 2;
     hipLaunchKernelGGL(k_validate, dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, cnt, dCraw,
-                       c->sc, c->part, c->counter);
+                       c->sc, c->part, c->counter, mm);
     HIP_TRY(hipGetLastError());
     std::vector<int32_t> hcnt(n);
     HIP_TRY(hipMemcpyAsync(hcnt.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> hmm((size_t)c->G * 4);
+    HIP_TRY(hipMemcpyAsync(hmm.data(), mm, sizeof(double) * 4 * c->G, hipMemcpyDeviceToHost, c->stream));
     DevScalars hsc;
     HIP_TRY(hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -375,6 +442,25 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     if (!(cF > 0.0)) cF = 1.0;
     c->c_F = c->prm.scale ? cF : 1.0;
     c->alpha_s = c->prm.scale ? 1.0 : alpha;
+    // storage format of the off-diagonal values
+    double vmin = INFINITY, vmax = -INFINITY, amin = INFINITY, amax = -INFINITY;
+    for (int g = 0; g < c->G; ++g) {
+        vmin = std::min(vmin, hmm[4 * g + 0]);
+        vmax = std::max(vmax, -hmm[4 * g + 1]);
+        amin = std::min(amin, hmm[4 * g + 2]);
+        amax = std::max(amax, -hmm[4 * g + 3]);
+    }
+    c->fmt = FMT_VAL;
+    c->cval = 1.0;
+    if (c->prm.matrix_format != 1 && std::isfinite(vmin)) {   // some off-diagonal entry exists
+        if (vmin == vmax) {
+            c->fmt = FMT_PAT;
+            c->cval = vmin / c->c_F;
+        } else if (amin == amax && amin > 0.0) {
+            c->fmt = FMT_SGN;
+            c->cval = amin / c->c_F;
+        }
+    }
     std::vector<int32_t> hrp_off(n + 1);
     int64_t acc = 0;
     for (int64_t r = 0; r < n; ++r) {
@@ -387,29 +473,35 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     std::vector<int32_t> hrb;
     partition_rows(hrp_off, n, hrb);
     c->nrb = (int)hrb.size() - 1;
-    c->Gs = std::min(kGMax, std::max(8, round8(c->nrb)));
+    c->Gs = std::min(kGMax, std::max(8, round8((c->nrb + kWaves - 1) / kWaves)));
     c->lanes = pick_lanes(n > 0 ? (double)acc / (double)n : 1.0);
     HIP_TRY(hipMemcpyAsync(c->rp, hrp_off.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->rb, hrb.data(), sizeof(int32_t) * hrb.size(), hipMemcpyHostToDevice, c->stream));
     const double inv_cF = 1.0 / c->c_F;
     const double inv_alpha = c->prm.scale ? 1.0 / alpha : 1.0;
     hipLaunchKernelGGL((k_scatter<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, c->rp,
-                       c->col, (T*)c->val, dCraw, c->dC, c->b, inv_cF, inv_alpha);
+                       c->col, (T*)c->val, dCraw, c->dC, c->b, inv_cF, inv_alpha, c->fmt);
     HIP_TRY(hipGetLastError());
     if (omega) {
         transpose_cast<double, T>(c, omega, (T*)c->Om, 1);
     } else {
         const int64_t total = (n + 3) / 4 * c->prm.R;
         const int g = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (total + kBlock - 1) / kBlock));
-        hipLaunchKernelGGL((k_omega<T>), dim3(g), dim3(kBlock), 0, c->stream, n, c->prm.R, c->prm.seed,
+        hipLaunchKernelGGL((k_omega<T>), dim3(g), dim3(kBlock), 0, c->stream, n, c->ld, c->prm.R, c->prm.seed,
                            (uint64_t)c->prm.instance, (T*)c->Om);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));   // dCraw (in z) is consumed before z is zeroed
     HIP_TRY(hipMemsetAsync(c->z, 0, 8 * n, c->stream));
     HIP_TRY(hipMemsetAsync(c->y, 0, 8 * n, c->stream));
-    HIP_TRY(hipMemsetAsync(c->S, 0, elem_size(c->prm) * n * c->prm.R, c->stream));
+    HIP_TRY(hipMemsetAsync(c->S, 0, elem_size(c->prm) * c->ld * c->prm.R, c->stream));
     HIP_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->prm.autotune && c->nnz_off >= (1 << 20)) {
+        scg_status st = autotune_lanes<T>(c);
+        if (st != SCG_OK) return st;
+        HIP_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
+    }
     HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * c->prm.T, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->t_next = 1;
@@ -449,6 +541,8 @@ void scg_default_params(scg_params* p) {
     p->reorth = 0;
     p->precision = SCG_FP64;
     p->instance = 0;
+    p->matrix_format = 0;
+    p->autotune = 1;
 }
 
 scg_status scg_workspace_size(const scg_params* p, int64_t n, int64_t nnz, size_t* bytes) {
@@ -475,6 +569,7 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->stream = (hipStream_t)stream;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return SCG_EHIP; }
     c->qmax = qmax_for(*p, n);
+    c->ld = (n + 63) / 64 * 64;
     c->G = std::min(kGMax, std::max(8, round8((n + 1023) / 1024)));
     char* base = (char*)workspace;
     c->rp = (int32_t*)(base + L.rp);
@@ -614,7 +709,7 @@ scg_status sketchycgal_apply(scg_ctx* c, const double* x, double* y) {
     const int64_t n = c->n;
     if (c->prm.precision == SCG_FP32_STREAM) {
         enqueue_prep<float>(c, it);
-        float* xs = (float*)c->V + n;
+        float* xs = (float*)c->V + c->ld;
         cast<double, float>(c, n, x, xs);
         launch_spmv<float, SPMV_APPLY>(c, xs, 0);
         cast<float, double>(c, n, (const float*)c->u, y);
@@ -630,8 +725,7 @@ scg_status sketchycgal_apply(scg_ctx* c, const double* x, double* y) {
 
 scg_status sketchycgal_time_spmv(scg_ctx* c, int32_t reps, double* avg_ms) {
     if (!c || reps < 1 || !avg_ms) return SCG_EINVAL;
-    if (c->t_next > c->prm.T) return SCG_ESTATE;
-    const IterArgs it = iter_args(c, c->t_next);
+    const IterArgs it = iter_args(c, std::min(c->t_next, c->prm.T));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));

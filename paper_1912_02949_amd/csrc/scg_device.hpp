@@ -91,23 +91,34 @@ __device__ bool grid_sum(const double (&val)[W], double* part, unsigned* counter
 }
 
 // Sum of W partials per producer workgroup written by the previous kernel in
-// the stream (part[g * W + w], g < nparts), in producer order; every thread
-// of the calling workgroup gets the totals.  The kernel boundary makes the
+// the stream (part[g * W + w], g < nparts), in a fixed order; every thread of
+// the calling workgroup gets the totals.  The kernel boundary makes the
 // producer's plain stores visible on every XCD, so no fence is needed and
-// each consumer workgroup computes bitwise-identical totals.
+// each consumer workgroup computes bitwise-identical totals.  Loads are
+// issued several producers at a time so their latencies overlap.
 template <int W>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nparts, double (&out)[W]) {
     __shared__ double red[kWaves];
+    double s[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        double s = 0.0;
-        for (int g = threadIdx.x; g < nparts; g += blockDim.x) s += part[(size_t)g * W + w];
-        if (blockDim.x == kBlock) {
-            out[w] = block_sum(s, red);
-        } else {   // one wave
-            out[w] = wave_sum(s);
+    for (int w = 0; w < W; ++w) s[w] = 0.0;
+    const int stride = blockDim.x;
+    constexpr int U = (W >= 4) ? 2 : 8;
+    for (int g0 = threadIdx.x; g0 < nparts; g0 += U * stride) {
+        double t[U][W];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = g0 + u * stride;
+#pragma unroll
+            for (int w = 0; w < W; ++w) t[u][w] = (g < nparts) ? part[(size_t)g * W + w] : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int w = 0; w < W; ++w) s[w] += t[u][w];
     }
+#pragma unroll
+    for (int w = 0; w < W; ++w) out[w] = (blockDim.x == kBlock) ? block_sum(s[w], red) : wave_sum(s[w]);
 }
 
 // Store this workgroup's W partial sums (thread 0 writes after the block sums).
@@ -118,6 +129,61 @@ __device__ __forceinline__ void write_partials(const double (&val)[W], double* p
     for (int w = 0; w < W; ++w) {
         const double bs = block_sum(val[w], red);
         if (threadIdx.x == 0) part[(size_t)blockIdx.x * W + w] = bs;
+    }
+}
+
+// LDS ordering among the lanes of one wave (a wave executes its LDS
+// operations in order; the barrier keeps the compiler from reordering).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------- 4-row vector access
+// Streaming kernels walk their rows in aligned quads (4 consecutive rows),
+// so FP32 data moves as 16-byte loads/stores and FP64 data as two 16-byte
+// accesses.  Every array starts 256-byte aligned and column strides are
+// multiples of 64 elements, so a quad at row 4i is always 16-byte aligned.
+// m < 4 marks the tail quad, handled element by element.
+__device__ __forceinline__ void ld4(const float* p, int m, double (&o)[4]) {
+    if (m == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = (j < m) ? (double)p[j] : 0.0;
+    }
+}
+__device__ __forceinline__ void ld4(const double* p, int m, double (&o)[4]) {
+    if (m == 4) {
+        const double2 a = reinterpret_cast<const double2*>(p)[0];
+        const double2 b = reinterpret_cast<const double2*>(p)[1];
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = (j < m) ? p[j] : 0.0;
+    }
+}
+// Stores round to the array's type; the rounded values are returned in v.
+__device__ __forceinline__ void st4(float* p, int m, double (&v)[4]) {
+    float t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { t[j] = (float)v[j]; v[j] = (double)t[j]; }
+    if (m == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(t[0], t[1], t[2], t[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) if (j < m) p[j] = t[j];
+    }
+}
+__device__ __forceinline__ void st4(double* p, int m, double (&v)[4]) {
+    if (m == 4) {
+        reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+        reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) if (j < m) p[j] = v[j];
     }
 }
 

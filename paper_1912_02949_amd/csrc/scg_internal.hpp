@@ -9,9 +9,16 @@ namespace scg {
 
 constexpr int kQCap = 512;     // maximum Lanczos steps per call
 constexpr int kRMax = 32;      // maximum sketch size R
-constexpr int kNB = 2048;      // nonzeros staged through LDS per row block
-constexpr int kRowsCap = 512;  // rows per row block
+constexpr int kNB = 512;       // nonzeros staged through LDS per row block (one wave)
+constexpr int kRowsCap = 128;  // rows per row block
 constexpr int kGMax = 2048;    // workgroups of a streaming launch
+
+// Storage of the off-diagonal values of C.
+enum MatFmt {
+    FMT_VAL = 0,   // one value per nonzero
+    FMT_PAT = 1,   // every off-diagonal value equals cval: columns only
+    FMT_SGN = 2    // every |value| equals cval: column with the sign in bit 31
+};
 
 // Scalars of the current iteration, resident in device memory.  Indexing of
 // the Lanczos run: basis vector V[j] (j = 0 .. k-1) is stored unnormalised;
@@ -42,16 +49,18 @@ struct Prob {
     const int32_t* rp;    // off-diagonal CSR, int32[n+1]
     const int32_t* col;
     const T* val;
+    double cval;          // the common (absolute) off-diagonal value, FMT_PAT / FMT_SGN
     const double* dC;     // diagonal of C (scaled)
     const double* b;      // scaled b
     double* z;
     double* y;
     T* s;                 // diagonal shift of D: dC + y + beta (z - b)
-    T* V;                 // Lanczos basis, (qmax+1) columns of n
+    int64_t ld;           // column stride of V, Omega, S: n rounded up to 64
+    T* V;                 // Lanczos basis, (qmax+1) columns of stride ld
     T* u;                 // SpMV output
     T* v;                 // Ritz vector (unnormalised)
-    const T* Om;          // Omega, n x R column-major (column c at c*n)
-    T* S;                 // sketch, n x R column-major
+    const T* Om;          // Omega, n x R column-major (column c at c*ld)
+    T* S;                 // sketch, n x R column-major (column c at c*ld)
     const int32_t* rb;    // row-block boundaries, int32[nrb+1]
     int nrb;
     DevScalars* sc;
@@ -74,6 +83,7 @@ struct Prob {
 struct scg_ctx {
     scg_params prm;
     int64_t n, nnz_in, nnz_off;
+    int64_t ld;     // padded column stride of V, Omega, S
     hipStream_t stream;
     int device;
     int t_next;
@@ -81,6 +91,8 @@ struct scg_ctx {
     int G;          // workgroups for vector kernels
     int Gs;         // workgroups for SpMV kernels
     int lanes;      // lanes per row in the SpMV row reduction
+    int fmt;        // MatFmt of the off-diagonal part
+    double cval;    // common (absolute) off-diagonal value, scaled
     int nrb;
     double alpha_orig;
     double c_F;

@@ -43,6 +43,26 @@ struct IterArgs {
     uint64_t instance;
 };
 
+// Streaming (read-once) data is loaded nontemporally so it does not evict
+// the gathered x entries from L2.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load_vals4(const float* p, float (&v)[4]) {
+    const f32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(p));
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void load_vals4(const double* p, double (&v)[4]) {
+    const f64x2_t a = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(p));
+    const f64x2_t b = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(p) + 1);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ int4 load_cols4(const int* p) {
+    const i32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(p));
+    return make_int4(t.x, t.y, t.z, t.w);
+}
+
 template <int LANES, typename A>
 __device__ __forceinline__ A group_sum(A v) {
 #pragma unroll
@@ -62,15 +82,78 @@ __device__ __forceinline__ bool lanczos_breakdown(double rho, double om, double 
 // OBJ: x = Ritz vector, xs = 1/||v|| (from k_ritz_fin); partial sums of
 //   x_hat^T C x_hat and ||D x_hat - xi x_hat||^2.
 // APPLY: u = D x, no scaling or reduction.
-template <typename T, int LANES, int MODE, int RB>
+//
+// Work unit: a row block of at most kNB nonzeros and kRowsCap rows, owned by
+// one wave64 with its own LDS slice, so waves never wait on each other:
+//   (A) lanes load values and columns as aligned 16-byte quads, gather x,
+//       stage the products in LDS, and load x_r, s_r and the row offsets;
+//   (B) LANES lanes per row add the staged products (LDS only);
+//   (C) one lane per row applies the shift and stores u (coalesced).
+// A row with more than kNB nonzeros is a row block of its own; the wave
+// strides over it.  The waves of a workgroup own consecutive row-block
+// ranges; the XCD-aware renumbering keeps each XCD on a contiguous eighth
+// of the rows.
+template <typename T>
+__device__ __forceinline__ T nt_load(const T* p) { return __builtin_nontemporal_load(p); }
+
+// Product of nonzero e (column word cw) with x, by storage format; the
+// common value of FMT_PAT / FMT_SGN is applied once per row instead.
+template <typename T, int FMT>
+__device__ __forceinline__ T nz_product(const Prob<T>& P, const T* __restrict__ x, int e, int cw) {
+    if (FMT == FMT_VAL) return nt_load(P.val + e) * x[cw];
+    if (FMT == FMT_PAT) return x[cw];
+    const T xv = x[cw & 0x7fffffff];
+    return (cw < 0) ? -xv : xv;
+}
+
+template <typename T, int FMT>
+__device__ __forceinline__ void stage_quad(const Prob<T>& P, const T* __restrict__ x, int qe, int e0, int e1,
+                                           T* stage) {
+    const int eb = qe << 2;
+    if (eb >= e0 && eb + 4 <= e1) {
+        const int4 c4 = load_cols4(P.col + eb);
+        T* st = stage + (eb - e0);
+        if (FMT == FMT_VAL) {
+            T v[4];
+            load_vals4(P.val + eb, v);
+            const T x0 = x[c4.x], x1 = x[c4.y], x2 = x[c4.z], x3 = x[c4.w];
+            st[0] = v[0] * x0;
+            st[1] = v[1] * x1;
+            st[2] = v[2] * x2;
+            st[3] = v[3] * x3;
+        } else if (FMT == FMT_PAT) {
+            st[0] = x[c4.x];
+            st[1] = x[c4.y];
+            st[2] = x[c4.z];
+            st[3] = x[c4.w];
+        } else {
+            const T x0 = x[c4.x & 0x7fffffff], x1 = x[c4.y & 0x7fffffff];
+            const T x2 = x[c4.z & 0x7fffffff], x3 = x[c4.w & 0x7fffffff];
+            st[0] = (c4.x < 0) ? -x0 : x0;
+            st[1] = (c4.y < 0) ? -x1 : x1;
+            st[2] = (c4.z < 0) ? -x2 : x2;
+            st[3] = (c4.w < 0) ? -x3 : x3;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = eb + i;
+            if (e >= e0 && e < e1) stage[e - e0] = nz_product<T, FMT>(P, x, e, nt_load(P.col + e));
+        }
+    }
+}
+
+template <typename T, int LANES, int MODE, int RB, int FMT>
 __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict__ x, int step) {
-    __shared__ T stage[kNB];
-    __shared__ T xrow[kRowsCap], srow[kRowsCap], rsum[kRowsCap];
-    __shared__ int rbeg[kRowsCap + 1];
+    __shared__ T stage_all[kWaves][kNB + 4];
+    __shared__ T xrow_all[kWaves][kRowsCap], srow_all[kWaves][kRowsCap], rsum_all[kWaves][kRowsCap];
+    __shared__ int rbeg_all[kWaves][kRowsCap + 1];
+    __shared__ double wred[kWaves][2];
     DevScalars* sc = P.sc;
+    if (MODE == SPMV_LANCZOS && sc->done) return;
     double xs = 1.0;
+    if (MODE == SPMV_OBJ) xs = sc->inv_vnorm;
     if (MODE == SPMV_LANCZOS) {
-        if (sc->done) return;
         if (step == 0) {
             double tot[kWPrep];
             reduce_partials<kWPrep>(P.p_prep, P.G, tot);
@@ -104,15 +187,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
                 sc->inv[step] = xs;
             }
         }
-    } else if (MODE == SPMV_OBJ) {
-        xs = sc->inv_vnorm;
     }
     const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T* stage = stage_all[wv];
+    T* xrow = xrow_all[wv];
+    T* srow = srow_all[wv];
+    T* rsum = rsum_all[wv];
+    int* rbeg = rbeg_all[wv];
     double acc0 = 0.0, acc1 = 0.0;
-    int64_t blo, bhi;
-    split_range(P.nrb, xcd_lid(), gridDim.x, blo, bhi);
-    const int tid = threadIdx.x;
-    auto finish_row = [&](int r, double off, double xr, double sr) {
+    const double cv = (FMT == FMT_VAL) ? 1.0 : P.cval;
+    auto finish_row = [&](int r, double off_raw, double xr, double sr) {
+        const double off = (FMT == FMT_VAL) ? off_raw : off_raw * cv;
         if (MODE == SPMV_LANCZOS) {
             const double uu = (off + sr * xr) * xs;
             const T ut = (T)uu;
@@ -128,54 +214,76 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
             P.u[r] = (T)(off + sr * xr);
         }
     };
+    int64_t blo, bhi;
+    split_range(P.nrb, xcd_lid() * kWaves + wv, gridDim.x * kWaves, blo, bhi);
     for (int64_t rbk = blo; rbk < bhi; ++rbk) {
         const int r0 = P.rb[rbk], r1 = P.rb[rbk + 1];
         const int e0 = P.rp[r0], e1 = P.rp[r1];
-        if (r1 - r0 == 1 && e1 - e0 > kNB) {
-            // one long row: the whole workgroup strides over it
+        const int nrows = r1 - r0;
+        if (nrows == 1 && e1 - e0 > kNB) {
             T a = 0;
-            for (int e = e0 + tid; e < e1; e += kBlock) a += P.val[e] * x[P.col[e]];
-            __shared__ double red[kWaves];
-            const double tot = block_sum((double)a, red);
-            if (tid == 0) finish_row(r0, tot, (double)x[r0], (double)P.s[r0]);
-            __syncthreads();
+            for (int e = e0 + lane; e < e1; e += 64) a += nz_product<T, FMT>(P, x, e, nt_load(P.col + e));
+            const double tot = wave_sum((double)a);
+            if (lane == 0) finish_row(r0, tot, (double)x[r0], (double)P.s[r0]);
             continue;
         }
-        // phase A: every global load of the row block, issued together
-        const int cnt = e1 - e0, nrows = r1 - r0;
-        for (int e = tid; e < cnt; e += kBlock) stage[e] = P.val[e0 + e] * x[P.col[e0 + e]];
-        for (int i = tid; i < nrows; i += kBlock) {
+        // (A)
+        const int q0 = e0 >> 2, q1 = (e1 + 3) >> 2;
+        for (int qe = q0 + lane; qe < q1; qe += 64) stage_quad<T, FMT>(P, x, qe, e0, e1, stage);
+        for (int i = lane; i < nrows; i += 64) {
             xrow[i] = x[r0 + i];
-            srow[i] = P.s[r0 + i];
-            rbeg[i] = P.rp[r0 + i] - e0;
+            srow[i] = nt_load(P.s + r0 + i);
+            rbeg[i] = nt_load(P.rp + r0 + i) - e0;
         }
-        if (tid == 0) rbeg[nrows] = cnt;
-        __syncthreads();
-        // phase B: LANES lanes per row reduce the staged products (LDS only)
-        const int g = tid / LANES, lane = tid % LANES;
-        for (int base = 0; base < nrows; base += kBlock / LANES) {
+        if (lane == 0) rbeg[nrows] = e1 - e0;
+        wave_sync();
+        // (B)
+        const int g = lane / LANES, sub = lane % LANES;
+        for (int base = 0; base < nrows; base += 64 / LANES) {
             const int i = base + g;
             T a = 0;
             if (i < nrows) {
                 const int a0 = rbeg[i], a1 = rbeg[i + 1];
-                for (int e = a0 + lane; e < a1; e += LANES) a += stage[e];
+                for (int e = a0 + sub; e < a1; e += LANES) a += stage[e];
             }
             a = group_sum<LANES>(a);
-            if (i < nrows && lane == 0) rsum[i] = a;
+            if (i < nrows && sub == 0) rsum[i] = a;
         }
-        __syncthreads();
-        // phase C: one thread per row, coalesced stores
-        for (int i = tid; i < nrows; i += kBlock) finish_row(r0 + i, (double)rsum[i], (double)xrow[i], (double)srow[i]);
-        __syncthreads();
+        wave_sync();
+        // (C)
+        for (int i = lane; i < nrows; i += 64) finish_row(r0 + i, (double)rsum[i], (double)xrow[i], (double)srow[i]);
+        wave_sync();
     }
-    if (MODE == SPMV_LANCZOS) {
-        double v[1] = {acc0};
-        write_partials<1>(v, P.p_spmv);
-    } else if (MODE == SPMV_OBJ) {
-        double v[2] = {acc0, acc1};
-        write_partials<2>(v, P.p_obj);
+    if (MODE == SPMV_APPLY) return;
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    if (lane == 0) {
+        wred[wv][0] = acc0;
+        wred[wv][1] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i < kWaves; ++i) {
+            s0 += wred[i][0];
+            s1 += wred[i][1];
+        }
+        if (MODE == SPMV_LANCZOS) {
+            P.p_spmv[blockIdx.x] = s0;
+        } else {
+            P.p_obj[(size_t)blockIdx.x * 2 + 0] = s0;
+            P.p_obj[(size_t)blockIdx.x * 2 + 1] = s1;
+        }
     }
 }
+
+// Rows of the workgroup's share in quads: for (qd...) { r = 4 qd; m = rows in quad }.
+#define SCG_FOR_QUADS(n)                                                   \
+    int64_t qlo_, qhi_;                                                    \
+    split_range(((n) + 3) / 4, xcd_lid(), gridDim.x, qlo_, qhi_);          \
+    for (int64_t qd = qlo_ + threadIdx.x; qd < qhi_; qd += kBlock)
+
+__device__ __forceinline__ int quad_rows(int64_t r, int64_t n) { return (int)((n - r < 4) ? (n - r) : 4); }
 
 // omega_step from the SpMV partials; w = u - omega v_step - rho v_{step-1}
 // stored as V[step+1]; partial sums of ||w||^2 (unless reorthogonalising).
@@ -183,6 +291,21 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lupdate(Prob<T> P, int step, int with_norm) {
     DevScalars* sc = P.sc;
     if (sc->done) return;
+    const int64_t n = P.n;
+    const T* vi = P.V + (size_t)step * P.ld;
+    const T* vm = (step > 0) ? P.V + (size_t)(step - 1) * P.ld : vi;
+    T* out = P.V + (size_t)(step + 1) * P.ld;
+    int64_t qlo, qhi;
+    split_range((n + 3) / 4, xcd_lid(), gridDim.x, qlo, qhi);
+    int64_t qd = qlo + threadIdx.x;
+    double u4[4], i4[4], m4[4];
+    if (qd < qhi) {   // first quad in flight before the omega reduction
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        ld4(P.u + r, m, u4);
+        ld4(vi + r, m, i4);
+        ld4(vm + r, m, m4);
+    }
     double tot[kWSpmv];
     reduce_partials<kWSpmv>(P.p_spmv, P.Gs, tot);
     const double om = tot[0];
@@ -194,19 +317,25 @@ __global__ __launch_bounds__(kBlock) void k_lupdate(Prob<T> P, int step, int wit
     const double si = sc->inv[step];
     const double rp = (step > 0) ? sc->rho[step - 1] : 0.0;
     const double sp = (step > 0) ? sc->inv[step - 1] : 0.0;
-    const int64_t n = P.n;
-    const T* vi = P.V + (size_t)step * n;
-    const T* vm = (step > 0) ? P.V + (size_t)(step - 1) * n : vi;
-    T* out = P.V + (size_t)(step + 1) * n;
-    int64_t lo, hi;
-    split_range(n, xcd_lid(), gridDim.x, lo, hi);
+    const double a1 = om * si, a2 = rp * sp;
     double acc = 0.0;
-    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-        double w = (double)P.u[r] - om * ((double)vi[r] * si);
-        if (step > 0) w -= rp * ((double)vm[r] * sp);
-        const T wt = (T)w;
-        out[r] = wt;
-        acc += (double)wt * (double)wt;
+    while (qd < qhi) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        double w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = u4[j] - a1 * i4[j] - a2 * m4[j];
+        st4(out + r, m, w);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc += w[j] * w[j];
+        qd += kBlock;
+        if (qd < qhi) {
+            const int64_t r2 = 4 * qd;
+            const int m2 = quad_rows(r2, n);
+            ld4(P.u + r2, m2, u4);
+            ld4(vi + r2, m2, i4);
+            ld4(vm + r2, m2, m4);
+        }
     }
     if (with_norm) {
         double v[1] = {acc};
@@ -221,12 +350,12 @@ __global__ __launch_bounds__(kBlock) void k_reorth_dot(Prob<T> P, int step) {
     if (sc->done) return;
     const int64_t n = P.n;
     const int nj = step + 1;
-    const T* w = P.V + (size_t)(step + 1) * n;
+    const T* w = P.V + (size_t)(step + 1) * P.ld;
     int64_t lo, hi;
     split_range(n, xcd_lid(), gridDim.x, lo, hi);
     __shared__ double red[kWaves];
     for (int j = 0; j < nj; ++j) {
-        const T* vj = P.V + (size_t)j * n;
+        const T* vj = P.V + (size_t)j * P.ld;
         double acc = 0.0;
         for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) acc += (double)vj[r] * (double)w[r];
         const double bs = block_sum(acc, red);
@@ -257,13 +386,13 @@ __global__ __launch_bounds__(kBlock) void k_reorth_apply(Prob<T> P, int step) {
     for (int j = threadIdx.x; j < nj; j += kBlock) hc[j] = sc->h[j] * sc->inv[j];
     __syncthreads();
     const int64_t n = P.n;
-    T* w = P.V + (size_t)(step + 1) * n;
+    T* w = P.V + (size_t)(step + 1) * P.ld;
     int64_t lo, hi;
     split_range(n, xcd_lid(), gridDim.x, lo, hi);
     double acc = 0.0;
     for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
         double a = 0.0;
-        for (int j = 0; j < nj; ++j) a += hc[j] * (double)P.V[(size_t)j * n + r];
+        for (int j = 0; j < nj; ++j) a += hc[j] * (double)P.V[(size_t)j * P.ld + r];
         const T wt = (T)((double)w[r] - a);
         w[r] = wt;
         acc += (double)wt * (double)wt;
@@ -275,9 +404,8 @@ __global__ __launch_bounds__(kBlock) void k_reorth_apply(Prob<T> P, int step) {
 // MinEvec of T_k and the Ritz coefficients coef_j = u_j inv_j.  One wave64.
 // Without breakdown the last SpMV's omega partials are still pending.
 template <typename T>
-__global__ __launch_bounds__(64) void k_tridiag(Prob<T> P, int q) {
-    __shared__ double d[kQCap], e[kQCap], e2[kQCap], wa[kQCap], wb[kQCap], wc[kQCap], wf[kQCap], x[kQCap];
-    __shared__ int piv[kQCap];
+__global__ __launch_bounds__(kBlock) void k_tridiag(Prob<T> P, int q) {
+    __shared__ double d[kQCap], e[kQCap], e2[kQCap], dp[kQCap], dm[kQCap], x[kQCap];
     __shared__ double xi;
     DevScalars* sc = P.sc;
     int k;
@@ -290,20 +418,21 @@ __global__ __launch_bounds__(64) void k_tridiag(Prob<T> P, int q) {
             sc->k = q;
             if (!isfinite(tot[0])) sc->flags |= 2;
         }
-        for (int i = threadIdx.x; i < k; i += 64) {
+        for (int i = threadIdx.x; i < k; i += kBlock) {
             d[i] = (i == q - 1) ? tot[0] : sc->omega[i];
             if (i < k - 1) e[i] = sc->rho[i];
         }
     } else {
         k = sc->k;
-        for (int i = threadIdx.x; i < k; i += 64) {
+        for (int i = threadIdx.x; i < k; i += kBlock) {
             d[i] = sc->omega[i];
             if (i < k - 1) e[i] = sc->rho[i];
         }
     }
     __syncthreads();
-    tridiag_min_eig(d, e, k, e2, wa, wb, wc, wf, piv, x, &xi);
-    for (int i = threadIdx.x; i < k; i += 64) sc->coef[i] = x[i] * sc->inv[i];
+    if (threadIdx.x < 64) tridiag_min_eig(d, e, k, e2, dp, dm, x, &xi);
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += kBlock) sc->coef[i] = x[i] * sc->inv[i];
     if (threadIdx.x == 0) {
         sc->xi = xi;
         if (!isfinite(xi)) sc->flags |= 2;
@@ -320,21 +449,30 @@ __global__ __launch_bounds__(kBlock) void k_ritz(Prob<T> P) {
     __syncthreads();
     const int64_t n = P.n;
     const int R = P.R;
-    int64_t lo, hi;
-    split_range(n, xcd_lid(), gridDim.x, lo, hi);
     double acc[RB + 1];
 #pragma unroll
     for (int c = 0; c <= RB; ++c) acc[c] = 0.0;
-    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-        double a = 0.0;
-        for (int j = 0; j < k; ++j) a += coef[j] * (double)P.V[(size_t)j * n + r];
-        const T vt = (T)a;
-        P.v[r] = vt;
-        const double vr = (double)vt;
-        acc[0] += vr * vr;
+    SCG_FOR_QUADS(n) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        double a[4] = {0, 0, 0, 0};
+        for (int j = 0; j < k; ++j) {
+            double t[4];
+            ld4(P.V + (size_t)j * P.ld + r, m, t);
+            const double cj = coef[j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] += cj * t[i];
+        }
+        st4(P.v + r, m, a);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[0] += a[i] * a[i];
 #pragma unroll
         for (int c = 0; c < RB; ++c)
-            if (c < R) acc[c + 1] += vr * (double)P.Om[(size_t)c * n + r];
+            if (c < R) {
+                double o[4];
+                ld4(P.Om + (size_t)c * P.ld + r, m, o);
+                acc[c + 1] += a[0] * o[0] + a[1] * o[1] + a[2] * o[2] + a[3] * o[3];
+            }
     }
     write_partials<RB + 1>(acc, P.p_ritz);
 }
@@ -362,29 +500,34 @@ __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
         sc->k = 0;
     }
     const int64_t n = P.n;
-    const int64_t ng = (n + 3) / 4;
-    int64_t lo, hi;
-    split_range(ng, xcd_lid(), gridDim.x, lo, hi);
     double a[kWPrep] = {0, 0, 0, 0, 0, 0};
-    for (int64_t gi = lo + threadIdx.x; gi < hi; gi += kBlock) {
-        double g[4];
-        normal4(it.seed, (uint64_t)gi, (uint64_t)it.t, it.instance, 0ull, g);
+    SCG_FOR_QUADS(n) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        double g[4], z4[4], y4[4], b4[4], d4[4], s4[4];
+        normal4(it.seed, (uint64_t)qd, (uint64_t)it.t, it.instance, 0ull, g);
+        ld4(P.z + r, m, z4);
+        ld4(P.y + r, m, y4);
+        ld4(P.b + r, m, b4);
+        ld4(P.dC + r, m, d4);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int64_t r = 4 * gi + m;
-            if (r >= n) break;
-            const double zr = P.z[r], yr = P.y[r], br = P.b[r];
-            const double zb = zr - br;
-            P.s[r] = (T)(P.dC[r] + (yr + it.beta * zb));
-            const T gt = (T)g[m];
-            P.V[r] = gt;
-            a[0] += (double)gt * (double)gt;
-            a[1] += yr * br;
-            a[2] += zb * (zr + br);
-            a[3] += (yr + it.beta * zb) * zr;
-            a[4] += zb * zb;
-            a[5] += br * br;
+        for (int j = 0; j < 4; ++j) {
+            const double zb = z4[j] - b4[j];
+            s4[j] = d4[j] + (y4[j] + it.beta * zb);
+            if (j < m) {
+                a[1] += y4[j] * b4[j];
+                a[2] += zb * (z4[j] + b4[j]);
+                a[3] += (y4[j] + it.beta * zb) * z4[j];
+                a[4] += zb * zb;
+                a[5] += b4[j] * b4[j];
+            } else {
+                g[j] = 0.0;
+            }
         }
+        st4(P.s + r, m, s4);
+        st4(P.V + r, m, g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[0] += g[j] * g[j];
     }
     write_partials<kWPrep>(a, P.p_prep);
 }
@@ -393,33 +536,43 @@ __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_primal(Prob<T> P, IterArgs it) {
     DevScalars* sc = P.sc;
-    double tot[kWObj];
-    reduce_partials<kWObj>(P.p_obj, P.Gs, tot);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->cv = tot[0];
-        sc->resid2 = tot[1];
-        if (!isfinite(tot[0])) sc->flags |= 2;
-    }
     const double iv = sc->inv_vnorm;
     const double ea = it.eta * it.alpha;
     const double keep = 1.0 - it.eta;
     const bool guard = isfinite(it.K);
-    int64_t lo, hi;
-    split_range(P.n, xcd_lid(), gridDim.x, lo, hi);
+    const int64_t n = P.n;
     double a[kWPrimal] = {0, 0, 0};
-    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-        const double vh = (double)P.v[r] * iv;
-        const double zn = keep * P.z[r] + ea * (vh * vh);
-        P.z[r] = zn;
-        const double d = zn - P.b[r];
-        a[0] += d * d;
-        if (guard) {
-            const double yr = P.y[r];
-            a[1] += yr * yr;
-            a[2] += yr * d;
+    SCG_FOR_QUADS(n) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        double v4[4], z4[4], b4[4], y4[4];
+        ld4(P.v + r, m, v4);
+        ld4(P.z + r, m, z4);
+        ld4(P.b + r, m, b4);
+        if (guard) ld4(P.y + r, m, y4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double vh = v4[j] * iv;
+            z4[j] = keep * z4[j] + ea * (vh * vh);
+            const double dd = (j < m) ? z4[j] - b4[j] : 0.0;
+            a[0] += dd * dd;
+            if (guard) {
+                a[1] += y4[j] * y4[j];
+                a[2] += y4[j] * dd;
+            }
         }
+        st4(P.z + r, m, z4);
     }
     write_partials<kWPrimal>(a, P.p_primal);
+    if (blockIdx.x == 0) {   // v^T C v and the residual, recorded for the log
+        double tot[kWObj];
+        reduce_partials<kWObj>(P.p_obj, P.Gs, tot);
+        if (threadIdx.x == 0) {
+            sc->cv = tot[0];
+            sc->resid2 = tot[1];
+            if (!isfinite(tot[0])) sc->flags |= 2;
+        }
+    }
 }
 
 // Dual step size (eqn sketchy-cgal-dual-step), K guard, trackers and log;
@@ -427,6 +580,19 @@ __global__ __launch_bounds__(kBlock) void k_primal(Prob<T> P, IterArgs it) {
 template <typename T, int RB>
 __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) {
     DevScalars* sc = P.sc;
+    const int64_t n = P.n;
+    int64_t qlo, qhi;
+    split_range((n + 3) / 4, xcd_lid(), gridDim.x, qlo, qhi);
+    int64_t qd = qlo + threadIdx.x;
+    double y4[4], z4[4], b4[4], v4[4];
+    if (qd < qhi) {   // first quad in flight before the reduction
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        ld4(P.y + r, m, y4);
+        ld4(P.z + r, m, z4);
+        ld4(P.b + r, m, b4);
+        ld4(P.v + r, m, v4);
+    }
     double tot[kWPrimal];
     reduce_partials<kWPrimal>(P.p_primal, P.G, tot);
     const double r2 = tot[0];
@@ -475,18 +641,35 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
     double cw[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) cw[c] = (c < R) ? sc->comega[c] : 0.0;
-    int64_t lo, hi;
-    split_range(P.n, xcd_lid(), gridDim.x, lo, hi);
-    const int64_t n = P.n;
-    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-        P.y[r] += gamma * (P.z[r] - P.b[r]);
-        const double vh = ea * ((double)P.v[r] * iv);
+    while (qd < qhi) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            y4[j] += gamma * (z4[j] - b4[j]);
+            v4[j] = ea * (v4[j] * iv);
+        }
+        st4(P.y + r, m, y4);
+        double s4[RB][4];
+#pragma unroll
+        for (int c = 0; c < RB; ++c)
+            if (c < R) ld4(P.S + (size_t)c * P.ld + r, m, s4[c]);
 #pragma unroll
         for (int c = 0; c < RB; ++c)
             if (c < R) {
-                T* sp = P.S + (size_t)c * n + r;
-                *sp = (T)(keep * (double)*sp + vh * cw[c]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) s4[c][j] = keep * s4[c][j] + v4[j] * cw[c];
+                st4(P.S + (size_t)c * P.ld + r, m, s4[c]);
             }
+        qd += kBlock;
+        if (qd < qhi) {
+            const int64_t r2 = 4 * qd;
+            const int m2 = quad_rows(r2, n);
+            ld4(P.y + r2, m2, y4);
+            ld4(P.z + r2, m2, z4);
+            ld4(P.b + r2, m2, b4);
+            ld4(P.v + r2, m2, v4);
+        }
     }
 }
 

@@ -75,7 +75,7 @@ __device__ void grid_sum_dyn(const double* lds_vals, int W, double* part, unsign
 
 // Pass 0: S^T S, Omega^T S, Omega^T Omega.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int R, const T* S, const T* Om, double* part,
+__global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int64_t ld, int R, const T* S, const T* Om, double* part,
                                                   unsigned* counter, double* small, Small L) {
     __shared__ double ts[kTile * kRMax], to[kTile * kRMax];
     __shared__ double acc_l[3 * kRMax * kRMax];
@@ -88,8 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int R, const T* S, 
         const int rows = (hi - t0 < kTile) ? (int)(hi - t0) : kTile;
         for (int e = threadIdx.x; e < rows * R; e += kBlock) {
             const int c = e / rows, rr = e % rows;   // column-major source
-            ts[rr * R + c] = (double)S[(int64_t)c * n + t0 + rr];
-            to[rr * R + c] = (double)Om[(int64_t)c * n + t0 + rr];
+            ts[rr * R + c] = (double)S[(int64_t)c * ld + t0 + rr];
+            to[rr * R + c] = (double)Om[(int64_t)c * ld + t0 + rr];
         }
         __syncthreads();
         int a = 0;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int R, const T* S, 
 // Pass B (sigma = 0, S = A in place): A_r = solve(Lk, A_r)
 // Both accumulate the Gram A^T A of the result.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_trsm_gram(int64_t n, int R, const T* S, const T* Om, double* A,
+__global__ __launch_bounds__(kBlock) void k_trsm_gram(int64_t n, int64_t ld, int R, const T* S, const T* Om, double* A,
                                                       int first, double* small, Small L, int lsel, double* part,
                                                       unsigned* counter) {
     __shared__ double tile[kTile * kRMax];
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_trsm_gram(int64_t n, int R, const T*
             const int64_t r = t0 + threadIdx.x;
             double x[kRMax];
             for (int c = 0; c < R; ++c)
-                x[c] = first ? ((double)S[(int64_t)c * n + r] + sigma * (double)Om[(int64_t)c * n + r])
+                x[c] = first ? ((double)S[(int64_t)c * ld + r] + sigma * (double)Om[(int64_t)c * ld + r])
                              : A[r * R + c];
             // forward substitution with the lower factor: Lm x_new = x
             for (int i = 0; i < R; ++i) {
@@ -376,13 +376,13 @@ scg_status recon_typed(scg_ctx* c, double* U, double* lambda, double* err) {
     const T* S = (const T*)c->S;
     const T* Om = (const T*)c->Om;
     const dim3 g(kGR), b(kBlock);
-    hipLaunchKernelGGL((k_gram0<T>), g, b, 0, c->stream, n, R, S, Om, part, c->counter, small, L);
+    hipLaunchKernelGGL((k_gram0<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, part, c->counter, small, L);
     hipLaunchKernelGGL(k_small_sigma, dim3(1), dim3(64), 0, c->stream, n, R, fp32, small, L);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, R, S, Om, A, 1, small, L, L.Lc, part, c->counter);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, A, 1, small, L, L.Lc, part, c->counter);
     hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, c->stream, n, R, small, L, L.L1, 1);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, R, S, Om, A, 0, small, L, L.L1, part, c->counter);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, A, 0, small, L, L.L1, part, c->counter);
     hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, c->stream, n, R, small, L, L.L2, 0);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, R, S, Om, A, 0, small, L, L.L2, part, c->counter);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, A, 0, small, L, L.L2, part, c->counter);
     hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, c->stream, n, R, small, L, L.L3, 0);
     // tau of the sketch (scaled units)
     DevScalars hsc;

@@ -3,13 +3,20 @@
 //   * eigenvalue: multisection on Sturm counts (each lane evaluates the
 //     LDL^T inertia count at one of 64 points; the interval shrinks 65-fold
 //     per round) until it is a few ulps wide;
-//   * eigenvector: inverse iteration with the tridiagonal LU factorisation
-//     with partial pivoting (row interchanges as in LAPACK's gttrf).
+//   * eigenvector: twisted factorisation of T - xi I (Dhillon and Parlett,
+//     "Multiple representations to compute orthogonal eigenvectors of
+//     symmetric tridiagonal matrices", LAA 387, 2004): the top-down LDL^T and
+//     bottom-up UDU^T pivots D+ and D- run on two lanes at once, the twist
+//     index r minimises |gamma_r| = |D+_r + D-_r - (d_r - xi)|, and the
+//     vector follows from u_r = 1 by the two one-sided recurrences.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <float.h>
 
+#include "scg_device.hpp"
+
 namespace scg {
+
 
 // 1/q for |q| >= pivmin (normal range): hardware reciprocal estimate refined by
 // two Newton steps, r <- r (2 - q r), which reach full double precision; the
@@ -36,34 +43,32 @@ __device__ inline int sturm_count(const double* d, const double* e2, int k, doub
     return cnt;
 }
 
-// d[k], e[k-1] in LDS (read-only), work: e2[k], lu arrays 4*k doubles, x[k].
-// Must be called by all 64 threads of the first wave; returns xi in every
-// lane and the unit eigenvector in x (sign: largest-magnitude entry > 0).
-__device__ void tridiag_min_eig(const double* d, const double* e, int k, double* e2, double* wa, double* wb,
-                                double* wc, double* wf, int* piv, double* x, double* xi_out) {
+// d[k], e[k-1] in LDS (read-only); work arrays e2, dp, dm, x of length k.
+// Must be called by all 64 threads of exactly one wave (no workgroup barrier inside); returns xi in every lane and
+// the unit eigenvector in x (sign: largest-magnitude entry positive).
+__device__ void tridiag_min_eig(const double* d, const double* e, int k, double* e2, double* dp, double* dm,
+                                double* x, double* xi_out) {
     const int lane = threadIdx.x & 63;
     if (k == 1) {
         if (lane == 0) { x[0] = 1.0; *xi_out = d[0]; }
-        __syncthreads();
+        wave_sync();
         return;
     }
-    // Gershgorin interval and |T| estimate
-    double lo = 1e308, hi = -1e308, emax2 = 0.0, tnorm = 0.0;
+    // Gershgorin interval
+    double lo = 1e308, hi = -1e308, emax2 = 0.0;
     for (int i = lane; i < k; i += 64) {
         const double el = (i > 0) ? fabs(e[i - 1]) : 0.0;
         const double er = (i < k - 1) ? fabs(e[i]) : 0.0;
         lo = fmin(lo, d[i] - el - er);
         hi = fmax(hi, d[i] + el + er);
-        tnorm = fmax(tnorm, fabs(d[i]) + el + er);
         if (i < k - 1) { e2[i] = e[i] * e[i]; emax2 = fmax(emax2, e2[i]); }
     }
     for (int off = 32; off > 0; off >>= 1) {
         lo = fmin(lo, __shfl_xor(lo, off, 64));
         hi = fmax(hi, __shfl_xor(hi, off, 64));
         emax2 = fmax(emax2, __shfl_xor(emax2, off, 64));
-        tnorm = fmax(tnorm, __shfl_xor(tnorm, off, 64));
     }
-    __syncthreads();
+    wave_sync();
     const double pivmin = DBL_MIN * fmax(1.0, emax2);
     const double pad = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 2.0 * pivmin;
     lo -= pad;
@@ -71,7 +76,7 @@ __device__ void tridiag_min_eig(const double* d, const double* e, int k, double*
     for (int it = 0; it < 64; ++it) {
         const double width = hi - lo;
         if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
-        const double xpt = lo + width * (double)(lane + 1) / 65.0;
+        const double xpt = lo + width * (double)(lane + 1) * (1.0 / 65.0);
         const int c = sturm_count(d, e2, k, xpt, pivmin);
         // smallest lane whose point has at least one eigenvalue below it
         const unsigned long long ballot = __ballot(c >= 1);
@@ -89,70 +94,65 @@ __device__ void tridiag_min_eig(const double* d, const double* e, int k, double*
         hi = nhi;
     }
     const double xi = 0.5 * (lo + hi);
-    if (lane == 0) {
-        // LU with partial pivoting of T - xi I: diag a, super b, sub c, 2nd super f
-        const double tiny = DBL_EPSILON * fmax(tnorm, DBL_MIN);
-        for (int i = 0; i < k; ++i) {
-            wa[i] = d[i] - xi;
-            if (i < k - 1) { wb[i] = e[i]; wc[i] = e[i]; }
-            wf[i] = 0.0;
+    // pivots of the two factorisations, lane 0 top-down, lane 1 bottom-up
+    if (lane < 2) {
+        const bool down = (lane == 0);
+        int i = down ? 0 : k - 1;
+        double q = d[i] - xi;
+        if (fabs(q) < pivmin) q = -pivmin;
+        (down ? dp : dm)[i] = q;
+        for (int st = 1; st < k; ++st) {
+            i = down ? st : k - 1 - st;
+            const double ee = down ? e2[i - 1] : e2[i];
+            q = (d[i] - xi) - ee * rcp_refined(q);
+            if (fabs(q) < pivmin) q = -pivmin;
+            (down ? dp : dm)[i] = q;
         }
-        for (int i = 0; i < k - 1; ++i) {
-            if (fabs(wa[i]) >= fabs(wc[i])) {
-                if (fabs(wa[i]) < tiny) wa[i] = (wa[i] < 0.0) ? -tiny : tiny;
-                const double m = wc[i] * rcp_refined(wa[i]);
-                wc[i] = m;
-                piv[i] = 0;
-                wa[i + 1] -= m * wb[i];
-            } else {
-                const double m = wa[i] * rcp_refined(wc[i]);
-                wa[i] = wc[i];
-                wc[i] = m;
-                piv[i] = 1;
-                const double t = wa[i + 1];
-                wa[i + 1] = wb[i] - m * t;
-                wb[i] = t;
-                if (i < k - 2) {
-                    wf[i] = wb[i + 1];
-                    wb[i + 1] = -m * wb[i + 1];
-                }
-            }
-        }
-        for (int i = 0; i < k; ++i) {
-            if (fabs(wa[i]) < tiny) wa[i] = (wa[i] < 0.0) ? -tiny : tiny;
-            wa[i] = rcp_refined(wa[i]);   // keep reciprocals of the pivots
-        }
-        // deterministic start vector with no special structure (golden-ratio sequence)
-        for (int i = 0; i < k; ++i) {
-            const double f = 0.6180339887498949 * (double)(i + 1);
-            x[i] = 1.0 + 0.5 * (f - floor(f));
-        }
-        for (int rep = 0; rep < 3; ++rep) {
-            // forward: apply row interchanges and multipliers
-            for (int i = 0; i < k - 1; ++i) {
-                if (piv[i] == 0) {
-                    x[i + 1] -= wc[i] * x[i];
-                } else {
-                    const double t = x[i];
-                    x[i] = x[i + 1];
-                    x[i + 1] = t - wc[i] * x[i + 1];
-                }
-            }
-            // backward substitution with U (diag a, super b, second super f)
-            x[k - 1] *= wa[k - 1];
-            if (k >= 2) x[k - 2] = (x[k - 2] - wb[k - 2] * x[k - 1]) * wa[k - 2];
-            for (int i = k - 3; i >= 0; --i) x[i] = (x[i] - wb[i] * x[i + 1] - wf[i] * x[i + 2]) * wa[i];
-            double nrm = 0.0, big = 0.0;
-            for (int i = 0; i < k; ++i) {
-                nrm += x[i] * x[i];
-                if (fabs(x[i]) > fabs(big)) big = x[i];
-            }
-            const double sc = (big < 0.0 ? -1.0 : 1.0) * rsqrt(nrm);
-            for (int i = 0; i < k; ++i) x[i] *= sc;
-        }
-        *xi_out = xi;
     }
-    __syncthreads();
+    wave_sync();
+    // twist index: argmin |gamma_i|, lowest index on ties
+    double best = 1e308;
+    int bi = 0;
+    for (int i = lane; i < k; i += 64) {
+        const double g = fabs(dp[i] + dm[i] - (d[i] - xi));
+        if (g < best) { best = g; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int r = bi;
+    if (lane < 2) {
+        const bool up = (lane == 0);   // lane 0: rows r-1 .. 0, lane 1: rows r+1 .. k-1
+        double u = 1.0;
+        if (up) x[r] = 1.0;
+        const int len = up ? r : k - 1 - r;
+        const int lmax = (r > k - 1 - r) ? r : k - 1 - r;
+        for (int st = 1; st <= lmax; ++st) {
+            if (st <= len) {
+                const int i = up ? r - st : r + st;
+                u = up ? -(e[i] * rcp_refined(dp[i])) * u : -(e[i - 1] * rcp_refined(dm[i])) * u;
+                x[i] = u;
+            }
+        }
+    }
+    wave_sync();
+    double nrm = 0.0, big = 0.0;
+    for (int i = lane; i < k; i += 64) {
+        nrm += x[i] * x[i];
+        if (fabs(x[i]) > fabs(big)) big = x[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nrm += __shfl_xor(nrm, off, 64);
+        const double ob = __shfl_xor(big, off, 64);
+        if (fabs(ob) > fabs(big) || (fabs(ob) == fabs(big) && ob > big)) big = ob;
+    }
+    const double sc = (big < 0.0 ? -1.0 : 1.0) / sqrt(nrm);
+    wave_sync();
+    for (int i = lane; i < k; i += 64) x[i] *= sc;
+    if (lane == 0) *xi_out = xi;
+    wave_sync();
 }
 
 }  // namespace scg

