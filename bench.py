@@ -155,6 +155,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only the SpMV kernel leg (for rocprofv3 --pmc) plus a 256 MiB device copy whose "
+                         "counters calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path is a design "
@@ -171,6 +174,22 @@ def main():
     p32 = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp32")
     p64 = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp64")
 
+    if args.traffic_probe:
+        sp = Solve(inst, p32, torch)
+        sp.init()
+        sp.lib.sketchycgal_step(sp.ctx, 2)
+        ms = C.c_double()
+        sp.lib.sketchycgal_time_spmv(sp.ctx, 20, C.byref(ms))
+        sp.close()
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"spmv_avg_us": ms.value * 1e3, "copy_bytes": 4 * a.numel(),
+                          "kernel_source_sha": kernel_source_sha()}), flush=True)
+        return
+
     s32 = Solve(inst, p32, torch)
     dt32 = timed(s32, args.steps, args.warmup, torch)
     sum32 = s32.summary()
@@ -181,8 +200,10 @@ def main():
     s32.close()
     nnz_off = inst.nnz - inst.n
     n = inst.n
-    # values + int32 columns, int32 row pointers, x (once), shift s, u written
-    bytes_per_launch = 8 * nnz_off + 4 * (n + 1) + 4 * n + 4 * n + 4 * n
+    # per nonzero: int32 column word (+ FP32 value when values are stored); per row: int32 row
+    # pointer, x (each entry once), shift s, u written
+    per_nz = 4 + (4 if sum32["matrix_format"] == 0 else 0)
+    bytes_per_launch = per_nz * nnz_off + 4 * (n + 1) + 4 * n + 4 * n + 4 * n
     achieved = bytes_per_launch / (spmv_ms * 1e-3) / 1e9
 
     traffic = None
@@ -238,6 +259,8 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_us": spmv_ms * 1e3,
         },
+        "spmv_tuning": {"lanes_per_row": sum32["spmv_lanes"], "column_segments": sum32["spmv_segments"],
+                        "matrix_format": ["values", "columns only", "columns with sign bit"][sum32["matrix_format"]]},
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "result_fp32": {"objective": sum32["objective"], "infeasibility": sum32["infeasibility"]},

@@ -71,7 +71,10 @@ typedef struct {
     int32_t  instance;      /* Philox counter word selecting this problem's random streams   */
     int32_t  matrix_format; /* 0: compress the off-diagonal values when they share one
                                magnitude (columns only, sign in bit 31); 1: always store values */
-    int32_t  autotune;      /* 1: time the SpMV row-reduction variants at init, keep the fastest */
+    int32_t  autotune;      /* 1: time the SpMV variants (lanes per row, column segments) at
+                               init and keep the fastest                                      */
+    int32_t  segments;      /* column segments of the SpMV: 0 = chosen by the autotuner
+                               (1 below 1M nonzeros), or 1, 2, 4                              */
 } scg_params;
 
 /* One record per iteration t, in scaled units (see file comment).  Gap and
@@ -99,6 +102,11 @@ typedef struct {
     double objective;         /* <C, X>                                     */
     double infeasibility;     /* ||diag X - b||                             */
     double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
+    int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction               */
+    int32_t spmv_segments;    /* column segments of the SpMV                                   */
+    int32_t matrix_format;    /* storage of the off-diagonal values: 0 values, 1 columns only
+                                 (common value), 2 columns with sign bit (common magnitude)  */
+    int32_t pad;
 } scg_summary;
 
 typedef struct scg_ctx scg_ctx;

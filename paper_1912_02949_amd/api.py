@@ -34,13 +34,14 @@ class Params:
     instance: int = 0
     matrix_format: int = 0        # 0: compress equal-magnitude off-diagonal values; 1: keep values
     autotune: int = 1
+    segments: int = 0             # SpMV column segments: 0 auto, or 1, 2, 4
 
     def to_c(self) -> _lib.scg_params:
         p = _lib.scg_params()
         p.R, p.T, p.beta0, p.K, p.alpha = self.R, self.T, self.beta0, self.K, self.alpha
         p.seed, p.q_mode, p.q_fixed, p.scale = self.seed, self.q_mode, self.q_fixed, self.scale
         p.trace_correct, p.reorth, p.instance = self.trace_correct, self.reorth, self.instance
-        p.matrix_format, p.autotune = self.matrix_format, self.autotune
+        p.matrix_format, p.autotune, p.segments = self.matrix_format, self.autotune, self.segments
         p.precision = {"fp64": _lib.SCG_FP64, "fp32": _lib.SCG_FP32_STREAM}[self.precision]
         return p
 

@@ -56,7 +56,7 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     const size_t ld = (size_t)((n + 63) / 64 * 64);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    L.rp = take(sizeof(int32_t) * (n + 1));
+    L.rp = take(sizeof(int32_t) * (size_t)kSegMax * (n + 1));
     L.col = take(sizeof(int32_t) * (size_t)nnz);
     L.val = take(es * (size_t)nnz);
     L.dC = take(8 * n);
@@ -69,7 +69,7 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.v = take(es * n);
     L.Om = take(es * ld * R);
     L.S = take(es * ld * R);
-    L.rb = take(sizeof(int32_t) * (n + 2));
+    L.rb = take(sizeof(int2) * (size_t)kSegMax * (n + 2));
     L.sc = take(sizeof(DevScalars));
     const size_t pw = 14 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
     L.part = take(8 * (size_t)kGMax * pw);
@@ -125,12 +125,15 @@ template <typename T, int MODE, int RB, int FMT>
 void launch_spmv_f(scg_ctx* c, const T* x, int step, int lanes) {
     Prob<T> P = prob<T>(c);
     dim3 g(c->Gs), b(kBlock);
-    switch (lanes) {
-        case 2: hipLaunchKernelGGL((k_spmv<T, 2, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
-        case 4: hipLaunchKernelGGL((k_spmv<T, 4, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
-        case 8: hipLaunchKernelGGL((k_spmv<T, 8, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
-        case 16: hipLaunchKernelGGL((k_spmv<T, 16, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
-        default: hipLaunchKernelGGL((k_spmv<T, 32, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step); break;
+    for (int sgi = 0; sgi < c->nseg; ++sgi) {
+        SegArgs sg{c->rp_seg[sgi], c->rbd_seg[sgi], c->nrb_seg[sgi], sgi == 0, sgi == c->nseg - 1};
+        switch (lanes) {
+            case 2: hipLaunchKernelGGL((k_spmv<T, 2, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+            case 4: hipLaunchKernelGGL((k_spmv<T, 4, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+            case 8: hipLaunchKernelGGL((k_spmv<T, 8, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+            case 16: hipLaunchKernelGGL((k_spmv<T, 16, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+            default: hipLaunchKernelGGL((k_spmv<T, 32, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+        }
     }
 }
 
@@ -351,6 +354,19 @@ void cast(scg_ctx* c, int64_t cnt, const Tin* in, Tout* out) {
     hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(g), dim3(kBlock), 0, c->stream, cnt, in, out);
 }
 
+void partition_rows(const std::vector<int32_t>& rp, int64_t n, std::vector<int32_t>& rb);
+
+// Row blocks of at most kNB nonzeros and kRowsCap rows (a longer row is a
+// block of its own), as (first row, first nonzero) pairs; the last entry is
+// (n, end of the nonzeros).
+std::vector<int2> block_descriptors(const std::vector<int32_t>& rp, int64_t n) {
+    std::vector<int32_t> rb;
+    partition_rows(rp, n, rb);
+    std::vector<int2> d(rb.size());
+    for (size_t k = 0; k < rb.size(); ++k) d[k] = make_int2(rb[k], rp[rb[k]]);
+    return d;
+}
+
 void partition_rows(const std::vector<int32_t>& rp, int64_t n, std::vector<int32_t>& rb) {
     rb.clear();
     rb.push_back(0);
@@ -379,11 +395,103 @@ int pick_lanes(double mean_len) {
     return l;
 }
 
+// Per-row counts of off-diagonal entries in each of nseg column segments.
+__global__ __launch_bounds__(kBlock) void k_segcount(int64_t n, const int64_t* rp, const int32_t* col, int nseg,
+                                                     int64_t seglen, int32_t* cnt) {
+    int64_t lo, hi;
+    split_range(n, xcd_lid(), gridDim.x, lo, hi);
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+        int32_t cs[kSegMax] = {0, 0, 0, 0};
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int32_t j = col[e];
+            if ((int64_t)j == r) continue;
+            cs[(int)(j / seglen)]++;
+        }
+        for (int s = 0; s < nseg; ++s) cnt[(size_t)s * n + r] = cs[s];
+    }
+}
+
+// Scatter the off-diagonal entries into the segment layout (rp_s absolute).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_seg(int64_t n, const int64_t* rp, const int32_t* col,
+                                                        const double* val, int nseg, int64_t seglen,
+                                                        const int32_t* rps, int64_t rps_stride, int32_t* col_off,
+                                                        T* val_off, double inv_cF, int fmt) {
+    int64_t lo, hi;
+    split_range(n, xcd_lid(), gridDim.x, lo, hi);
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+        int32_t o[kSegMax];
+        for (int s = 0; s < nseg; ++s) o[s] = rps[(size_t)s * rps_stride + r];
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int32_t j = col[e];
+            if ((int64_t)j == r) continue;
+            const int s = (int)(j / seglen);
+            const int32_t at = o[s]++;
+            if (fmt == FMT_VAL) {
+                col_off[at] = j;
+                val_off[at] = (T)(val[e] * inv_cF);
+            } else if (fmt == FMT_PAT) {
+                col_off[at] = j;
+            } else {
+                col_off[at] = (val[e] < 0.0) ? (int32_t)((uint32_t)j | 0x80000000u) : j;
+            }
+        }
+    }
+}
+
+// Build the nseg-segment layout of the off-diagonal part from the input CSR.
+template <typename T>
+scg_status build_segments(scg_ctx* c, int nseg, const int64_t* row_ptr, const int32_t* col, const double* val) {
+    const int64_t n = c->n;
+    const int64_t seglen = (n + nseg - 1) / nseg;
+    int32_t* cnt = c->rb;   // scratch: nseg * n ints fit in the row-block area
+    hipLaunchKernelGGL(k_segcount, dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, nseg, seglen, cnt);
+    std::vector<int32_t> hc((size_t)nseg * n);
+    HIP_TRY(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * hc.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> hrp((size_t)nseg * (n + 1));
+    int64_t acc = 0;
+    for (int s = 0; s < nseg; ++s) {
+        for (int64_t r = 0; r < n; ++r) {
+            hrp[(size_t)s * (n + 1) + r] = (int32_t)acc;
+            acc += hc[(size_t)s * n + r];
+        }
+        hrp[(size_t)s * (n + 1) + n] = (int32_t)acc;
+    }
+    if (acc != c->nnz_off) return SCG_EINVAL;
+    int maxnrb = 0;
+    std::vector<std::vector<int2>> hrbd(nseg);
+    for (int s = 0; s < nseg; ++s) {
+        std::vector<int32_t> rps(hrp.begin() + (size_t)s * (n + 1), hrp.begin() + (size_t)(s + 1) * (n + 1));
+        hrbd[s] = block_descriptors(rps, n);
+        maxnrb = std::max(maxnrb, (int)hrbd[s].size() - 1);
+    }
+    for (int s = 0; s < nseg; ++s) {
+        c->rp_seg[s] = c->rp + (size_t)s * (n + 1);
+        c->rbd_seg[s] = reinterpret_cast<int2*>(c->rb) + (size_t)s * (n + 2);
+        c->nrb_seg[s] = (int)hrbd[s].size() - 1;
+        HIP_TRY(hipMemcpyAsync(c->rp_seg[s], hrp.data() + (size_t)s * (n + 1), sizeof(int32_t) * (n + 1),
+                               hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->rbd_seg[s], hrbd[s].data(), sizeof(int2) * hrbd[s].size(), hipMemcpyHostToDevice,
+                               c->stream));
+    }
+    c->nseg = nseg;
+    c->seglen = seglen;
+    c->nrb = maxnrb;
+    c->Gs = std::min(kGMax, std::max(8, round8((maxnrb + kWaves - 1) / kWaves)));
+    hipLaunchKernelGGL((k_scatter_seg<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, nseg, seglen,
+                       c->rp, (int64_t)(n + 1), c->col, (T*)c->val, 1.0 / c->c_F, c->fmt);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCG_OK;
+}
+
 // Autotuner: time the Lanczos SpMV for each lanes-per-row choice on this
 // matrix (after a k_prep of iteration 1 has filled the start vector and the
 // shift) and keep the fastest.  Timed with HIP events on the context stream.
+// and each column-segment count, and keep the fastest layout.
 template <typename T>
-scg_status autotune_lanes(scg_ctx* c) {
+scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, const double* val) {
     const IterArgs it = iter_args(c, 1);
     enqueue_prep<T>(c, it);
     hipEvent_t e0, e1;
@@ -391,20 +499,32 @@ scg_status autotune_lanes(scg_ctx* c) {
     HIP_TRY(hipEventCreate(&e1));
     const double mean = c->n > 0 ? (double)c->nnz_off / (double)c->n : 1.0;
     float best = 1e30f;
-    int best_l = c->lanes;
-    for (int l : {2, 4, 8, 16, 32}) {
-        if (l > 4 * mean + 4) break;
-        launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);   // warm-up
-        HIP_TRY(hipEventRecord(e0, c->stream));
-        for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);
-        HIP_TRY(hipEventRecord(e1, c->stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) { best = ms; best_l = l; }
+    int best_l = c->lanes, best_s = 1;
+    for (int nseg : {1, 2, 4}) {
+        if (c->prm.segments > 0 && nseg != c->prm.segments) continue;
+        if (nseg > 1) {
+            if (c->prm.segments == 0 && c->n < (1 << 18)) break;
+            scg_status st = build_segments<T>(c, nseg, row_ptr, col, val);
+            if (st != SCG_OK) return st;
+        }
+        for (int l : {2, 4, 8, 16, 32}) {
+            if (l > 4 * mean + 4) break;
+            launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);   // warm-up
+            HIP_TRY(hipEventRecord(e0, c->stream));
+            for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);
+            HIP_TRY(hipEventRecord(e1, c->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_l = l; best_s = nseg; }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (c->nseg != best_s) {
+        scg_status st = build_segments<T>(c, best_s, row_ptr, col, val);
+        if (st != SCG_OK) return st;
+    }
     c->lanes = best_l;
     return SCG_OK;
 }
@@ -470,13 +590,17 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     }
     hrp_off[n] = (int32_t)acc;
     c->nnz_off = acc;
-    std::vector<int32_t> hrb;
-    partition_rows(hrp_off, n, hrb);
-    c->nrb = (int)hrb.size() - 1;
+    std::vector<int2> hrbd = block_descriptors(hrp_off, n);
+    c->nrb = (int)hrbd.size() - 1;
     c->Gs = std::min(kGMax, std::max(8, round8((c->nrb + kWaves - 1) / kWaves)));
+    c->nseg = 1;
+    c->seglen = n;
+    c->rp_seg[0] = c->rp;
+    c->rbd_seg[0] = reinterpret_cast<int2*>(c->rb);
+    c->nrb_seg[0] = c->nrb;
     c->lanes = pick_lanes(n > 0 ? (double)acc / (double)n : 1.0);
     HIP_TRY(hipMemcpyAsync(c->rp, hrp_off.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->rb, hrb.data(), sizeof(int32_t) * hrb.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->rb, hrbd.data(), sizeof(int2) * hrbd.size(), hipMemcpyHostToDevice, c->stream));
     const double inv_cF = 1.0 / c->c_F;
     const double inv_alpha = c->prm.scale ? 1.0 / alpha : 1.0;
     hipLaunchKernelGGL((k_scatter<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, c->rp,
@@ -497,10 +621,13 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     HIP_TRY(hipMemsetAsync(c->S, 0, elem_size(c->prm) * c->ld * c->prm.R, c->stream));
     HIP_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (c->prm.autotune && c->nnz_off >= (1 << 20)) {
-        scg_status st = autotune_lanes<T>(c);
+    if (c->prm.autotune && (c->nnz_off >= (1 << 20) || c->prm.segments > 0)) {
+        scg_status st = autotune_spmv<T>(c, row_ptr, col, val);
         if (st != SCG_OK) return st;
         HIP_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
+    } else if (c->prm.segments > 1) {
+        scg_status st = build_segments<T>(c, c->prm.segments, row_ptr, col, val);
+        if (st != SCG_OK) return st;
     }
     HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * c->prm.T, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -543,6 +670,7 @@ void scg_default_params(scg_params* p) {
     p->instance = 0;
     p->matrix_format = 0;
     p->autotune = 1;
+    p->segments = 0;
 }
 
 scg_status scg_workspace_size(const scg_params* p, int64_t n, int64_t nnz, size_t* bytes) {
@@ -586,6 +714,7 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->Om = base + L.Om;
     c->S = base + L.S;
     c->rb = (int32_t*)(base + L.rb);
+    c->rb_cap = (size_t)kSegMax * (n + 2);
     c->sc = (DevScalars*)(base + L.sc);
     c->part = (double*)(base + L.part);
     c->counter = (unsigned*)(base + L.counter);
@@ -647,6 +776,10 @@ scg_status sketchycgal_summary(scg_ctx* c, scg_summary* o) {
     o->alpha_scaled = c->alpha_s;
     o->objective = c->c_F * c->alpha_orig * hsc.p / c->alpha_s;
     o->infeasibility = c->alpha_orig / c->alpha_s * infeas_s;
+    o->spmv_lanes = c->lanes;
+    o->spmv_segments = c->nseg;
+    o->matrix_format = c->fmt;
+    o->pad = 0;
     return (hsc.flags & 2) ? SCG_ENUMERIC : SCG_OK;
 }
 

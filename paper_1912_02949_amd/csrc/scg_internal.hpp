@@ -12,6 +12,7 @@ constexpr int kRMax = 32;      // maximum sketch size R
 constexpr int kNB = 512;       // nonzeros staged through LDS per row block (one wave)
 constexpr int kRowsCap = 128;  // rows per row block
 constexpr int kGMax = 2048;    // workgroups of a streaming launch
+constexpr int kSegMax = 4;     // column segments of the SpMV
 
 // Storage of the off-diagonal values of C.
 enum MatFmt {
@@ -91,6 +92,12 @@ struct scg_ctx {
     int G;          // workgroups for vector kernels
     int Gs;         // workgroups for SpMV kernels
     int lanes;      // lanes per row in the SpMV row reduction
+    int nseg;       // column segments (1, 2 or 4): launch s gathers only x[s*seglen, (s+1)*seglen)
+    int64_t seglen;
+    int32_t* rp_seg[scg::kSegMax];   // per segment: row pointers into col/val (absolute)
+    int2* rbd_seg[scg::kSegMax];     // per segment: row-block descriptors (first row, first nonzero)
+    int nrb_seg[scg::kSegMax];
+    size_t rb_cap;  // int2 entries available in the row-block area
     int fmt;        // MatFmt of the off-diagonal part
     double cval;    // common (absolute) off-diagonal value, scaled
     int nrb;

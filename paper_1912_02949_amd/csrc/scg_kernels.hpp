@@ -106,54 +106,112 @@ __device__ __forceinline__ T nz_product(const Prob<T>& P, const T* __restrict__ 
     return (cw < 0) ? -xv : xv;
 }
 
+// Values and column words of one row block, a few 16-byte quads per lane.
+constexpr int kQW = (kNB / 4 + 1 + 63) / 64;
+
 template <typename T, int FMT>
-__device__ __forceinline__ void stage_quad(const Prob<T>& P, const T* __restrict__ x, int qe, int e0, int e1,
-                                           T* stage) {
-    const int eb = qe << 2;
-    if (eb >= e0 && eb + 4 <= e1) {
-        const int4 c4 = load_cols4(P.col + eb);
-        T* st = stage + (eb - e0);
-        if (FMT == FMT_VAL) {
-            T v[4];
-            load_vals4(P.val + eb, v);
-            const T x0 = x[c4.x], x1 = x[c4.y], x2 = x[c4.z], x3 = x[c4.w];
-            st[0] = v[0] * x0;
-            st[1] = v[1] * x1;
-            st[2] = v[2] * x2;
-            st[3] = v[3] * x3;
-        } else if (FMT == FMT_PAT) {
-            st[0] = x[c4.x];
-            st[1] = x[c4.y];
-            st[2] = x[c4.z];
-            st[3] = x[c4.w];
-        } else {
-            const T x0 = x[c4.x & 0x7fffffff], x1 = x[c4.y & 0x7fffffff];
-            const T x2 = x[c4.z & 0x7fffffff], x3 = x[c4.w & 0x7fffffff];
-            st[0] = (c4.x < 0) ? -x0 : x0;
-            st[1] = (c4.y < 0) ? -x1 : x1;
-            st[2] = (c4.z < 0) ? -x2 : x2;
-            st[3] = (c4.w < 0) ? -x3 : x3;
-        }
-    } else {
+struct BlockRegs {
+    int4 c[kQW];
+    T v[(FMT == FMT_VAL) ? kQW : 1][4];
+};
+
+template <typename T, int FMT>
+__device__ __forceinline__ void fetch_block(const Prob<T>& P, int e0, int e1, int lane, BlockRegs<T, FMT>& B) {
+    const int q0 = e0 >> 2, q1 = (e1 + 3) >> 2;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = eb + i;
-            if (e >= e0 && e < e1) stage[e - e0] = nz_product<T, FMT>(P, x, e, nt_load(P.col + e));
+    for (int j = 0; j < kQW; ++j) {
+        const int qe = q0 + lane + 64 * j;
+        if (qe < q1) {
+            const int eb = qe << 2;
+            if (eb >= e0 && eb + 4 <= e1) {
+                B.c[j] = load_cols4(P.col + eb);
+                if (FMT == FMT_VAL) load_vals4(P.val + eb, B.v[FMT == FMT_VAL ? j : 0]);
+            } else {
+                int cc[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = eb + i;
+                    const bool ok = (e >= e0 && e < e1);
+                    cc[i] = ok ? nt_load(P.col + e) : 0;
+                    if (FMT == FMT_VAL) B.v[FMT == FMT_VAL ? j : 0][i] = ok ? nt_load(P.val + e) : (T)0;
+                }
+                B.c[j] = make_int4(cc[0], cc[1], cc[2], cc[3]);
+            }
         }
     }
 }
 
+template <typename T, int FMT>
+__device__ __forceinline__ T column_product(const T* __restrict__ x, int cw, T v) {
+    if (FMT == FMT_VAL) return v * x[cw];
+    if (FMT == FMT_PAT) return x[cw];
+    const T xv = x[cw & 0x7fffffff];
+    return (cw < 0) ? -xv : xv;
+}
+
+template <typename T, int FMT>
+__device__ __forceinline__ void stage_block(const T* __restrict__ x, int e0, int e1, int lane,
+                                            const BlockRegs<T, FMT>& B, T* stage) {
+    const int q0 = e0 >> 2, q1 = (e1 + 3) >> 2;
+#pragma unroll
+    for (int j = 0; j < kQW; ++j) {
+        const int qe = q0 + lane + 64 * j;
+        if (qe < q1) {
+            const int eb = qe << 2;
+            const int cc[4] = {B.c[j].x, B.c[j].y, B.c[j].z, B.c[j].w};
+            T pr[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pr[i] = column_product<T, FMT>(x, cc[i], FMT == FMT_VAL ? B.v[FMT == FMT_VAL ? j : 0][i] : (T)0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = eb + i;
+                if (e >= e0 && e < e1) stage[e - e0] = pr[i];
+            }
+        }
+    }
+}
+
+// One column segment of the product: the off-diagonal entries whose
+// columns fall in segment `seg`.  Launches over the segments run in order;
+// all but the last store the raw row sums in u, the later ones add them.
+// rbd[k] = (first row, first nonzero) of row block k; rbd[nrb] = (n, end).
+struct SegArgs {
+    const int32_t* rp;
+    const int2* rbd;
+    int nrb;
+    int first;
+    int last;
+};
+
 template <typename T, int LANES, int MODE, int RB, int FMT>
-__global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict__ x, int step) {
+__global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict__ x, int step, SegArgs sg) {
     __shared__ T stage_all[kWaves][kNB + 4];
     __shared__ T xrow_all[kWaves][kRowsCap], srow_all[kWaves][kRowsCap], rsum_all[kWaves][kRowsCap];
     __shared__ int rbeg_all[kWaves][kRowsCap + 1];
     __shared__ double wred[kWaves][2];
     DevScalars* sc = P.sc;
     if (MODE == SPMV_LANCZOS && sc->done) return;
+    P.rp = sg.rp;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T* stage = stage_all[wv];
+    T* xrow = xrow_all[wv];
+    T* srow = srow_all[wv];
+    T* rsum = rsum_all[wv];
+    int* rbeg = rbeg_all[wv];
+    int64_t blo, bhi;
+    split_range(sg.nrb, xcd_lid() * kWaves + wv, gridDim.x * kWaves, blo, bhi);
+    // first block's descriptors and nonzeros are requested before the scale reduction
+    int2 dA = make_int2(0, 0), dB = make_int2(0, 0), dC = make_int2(0, 0);
+    BlockRegs<T, FMT> cur;
+    if (blo < bhi) {
+        dA = sg.rbd[blo];
+        dB = sg.rbd[blo + 1];
+        if (blo + 1 < bhi) dC = sg.rbd[blo + 2];
+        if (!(dB.x - dA.x == 1 && dB.y - dA.y > kNB)) fetch_block<T, FMT>(P, dA.y, dB.y, lane, cur);
+    }
     double xs = 1.0;
     if (MODE == SPMV_OBJ) xs = sc->inv_vnorm;
-    if (MODE == SPMV_LANCZOS) {
+    if (MODE == SPMV_LANCZOS && sg.last) {
         if (step == 0) {
             double tot[kWPrep];
             reduce_partials<kWPrep>(P.p_prep, P.G, tot);
@@ -189,15 +247,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
         }
     }
     const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    T* stage = stage_all[wv];
-    T* xrow = xrow_all[wv];
-    T* srow = srow_all[wv];
-    T* rsum = rsum_all[wv];
-    int* rbeg = rbeg_all[wv];
     double acc0 = 0.0, acc1 = 0.0;
     const double cv = (FMT == FMT_VAL) ? 1.0 : P.cval;
     auto finish_row = [&](int r, double off_raw, double xr, double sr) {
+        if (!sg.first) off_raw += (double)P.u[r];
+        if (!sg.last) {
+            P.u[r] = (T)off_raw;
+            return;
+        }
         const double off = (FMT == FMT_VAL) ? off_raw : off_raw * cv;
         if (MODE == SPMV_LANCZOS) {
             const double uu = (off + sr * xr) * xs;
@@ -214,47 +271,52 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
             P.u[r] = (T)(off + sr * xr);
         }
     };
-    int64_t blo, bhi;
-    split_range(P.nrb, xcd_lid() * kWaves + wv, gridDim.x * kWaves, blo, bhi);
     for (int64_t rbk = blo; rbk < bhi; ++rbk) {
-        const int r0 = P.rb[rbk], r1 = P.rb[rbk + 1];
-        const int e0 = P.rp[r0], e1 = P.rp[r1];
+        const int r0 = dA.x, r1 = dB.x, e0 = dA.y, e1 = dB.y;
         const int nrows = r1 - r0;
+        const bool has_next = rbk + 1 < bhi;
+        const bool next_long = has_next && (dC.x - dB.x == 1 && dC.y - dB.y > kNB);
+        int2 dD = dC;
+        if (rbk + 2 < bhi) dD = sg.rbd[rbk + 3];
         if (nrows == 1 && e1 - e0 > kNB) {
             T a = 0;
             for (int e = e0 + lane; e < e1; e += 64) a += nz_product<T, FMT>(P, x, e, nt_load(P.col + e));
             const double tot = wave_sum((double)a);
             if (lane == 0) finish_row(r0, tot, (double)x[r0], (double)P.s[r0]);
-            continue;
-        }
-        // (A)
-        const int q0 = e0 >> 2, q1 = (e1 + 3) >> 2;
-        for (int qe = q0 + lane; qe < q1; qe += 64) stage_quad<T, FMT>(P, x, qe, e0, e1, stage);
-        for (int i = lane; i < nrows; i += 64) {
-            xrow[i] = x[r0 + i];
-            srow[i] = nt_load(P.s + r0 + i);
-            rbeg[i] = nt_load(P.rp + r0 + i) - e0;
-        }
-        if (lane == 0) rbeg[nrows] = e1 - e0;
-        wave_sync();
-        // (B)
-        const int g = lane / LANES, sub = lane % LANES;
-        for (int base = 0; base < nrows; base += 64 / LANES) {
-            const int i = base + g;
-            T a = 0;
-            if (i < nrows) {
-                const int a0 = rbeg[i], a1 = rbeg[i + 1];
-                for (int e = a0 + sub; e < a1; e += LANES) a += stage[e];
+        } else {
+            // (A) gathers for this block
+            stage_block<T, FMT>(x, e0, e1, lane, cur, stage);
+            for (int i = lane; i < nrows; i += 64) {
+                xrow[i] = x[r0 + i];
+                srow[i] = nt_load(P.s + r0 + i);
+                rbeg[i] = nt_load(P.rp + r0 + i) - e0;
             }
-            a = group_sum<LANES>(a);
-            if (i < nrows && sub == 0) rsum[i] = a;
+            if (lane == 0) rbeg[nrows] = e1 - e0;
+            wave_sync();
+            // (B)
+            const int g = lane / LANES, sub = lane % LANES;
+            for (int base = 0; base < nrows; base += 64 / LANES) {
+                const int i = base + g;
+                T a = 0;
+                if (i < nrows) {
+                    const int a0 = rbeg[i], a1 = rbeg[i + 1];
+                    for (int e = a0 + sub; e < a1; e += LANES) a += stage[e];
+                }
+                a = group_sum<LANES>(a);
+                if (i < nrows && sub == 0) rsum[i] = a;
+            }
+            wave_sync();
+            // (C)
+            for (int i = lane; i < nrows; i += 64)
+                finish_row(r0 + i, (double)rsum[i], (double)xrow[i], (double)srow[i]);
+            wave_sync();
         }
-        wave_sync();
-        // (C)
-        for (int i = lane; i < nrows; i += 64) finish_row(r0 + i, (double)rsum[i], (double)xrow[i], (double)srow[i]);
-        wave_sync();
+        if (has_next && !next_long) fetch_block<T, FMT>(P, dB.y, dC.y, lane, cur);
+        dA = dB;
+        dB = dC;
+        dC = dD;
     }
-    if (MODE == SPMV_APPLY) return;
+    if (MODE == SPMV_APPLY || !sg.last) return;
     acc0 = wave_sum(acc0);
     acc1 = wave_sum(acc1);
     if (lane == 0) {

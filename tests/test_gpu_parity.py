@@ -135,6 +135,32 @@ def test_trajectory_small_q_fp64(cfg1):
     assert rel(summ["infeasibility"], ref.infeasibility) < 1e-9
 
 
+@pytest.mark.parametrize("segments", [2, 4])
+@pytest.mark.parametrize("which", ["cfg1", "star", "pm1"])
+def test_apply_with_column_segments(which, segments, cfg1):
+    need_gpu()
+    inst = {"cfg1": lambda: cfg1, "star": lambda: _star_plus(5000, 3),
+            "pm1": lambda: synth.laplacian_instance(synth.torus_longrange(64, 5))}[which]()
+    s = make_solver(inst, R=4, T=5, seed=1, segments=segments)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(inst.n)
+    y = s.apply(x).cpu().numpy()
+    Cs, bs, _, _ = scale_problem(inst.to_scipy(), inst.b, float(inst.n))
+    ref = Cs @ x + math.sqrt(2.0) * (0 - bs) * x
+    assert maxrel(y, ref) < 1e-13
+
+
+def test_trajectory_with_column_segments_fp64(cfg1):
+    need_gpu()
+    kw = dict(R=10, T=40, seed=SEED1, q_mode=1, q_fixed=8)
+    s = make_solver(cfg1, segments=4, **kw)
+    s.run()
+    lg = s.log()
+    ref = oracle_run(cfg1, **kw)
+    assert maxrel(lg["p"], ref.log["p"]) < 1e-9
+    assert np.max(np.abs(lg["infeas"] - ref.log["infeas"]) / ref.log["infeas"]) < 1e-9
+
+
 def test_compressed_matrix_format_matches_values(cfg1):
     """Columns-only storage (unit weights) against stored values, FP64, q = 8."""
     need_gpu()
