@@ -188,6 +188,65 @@ scg_status sketchycgal_time_spmv(scg_ctx* ctx, int32_t reps, double* avg_ms);
 void sketchycgal_destroy(scg_ctx* ctx);
 const char* scg_status_string(scg_status s);
 
+/* ------------------------------------------------------------------------
+ * Batched engine: many independent MaxCut-type problems of uneven size, each
+ * solved by alg:sketchy-cgal with its own scaling (Section 7.1.1), its own
+ * random streams (Philox counter word params.instance + i for problem i) and
+ * its own iteration state, advanced together by ONE kernel launch per
+ * iteration.  The problems are given as one block-diagonal CSR matrix: rows
+ * of problem i are rows [r_i, r_i + inst_n[i]) with r_i = sum_{j<i} inst_n[j],
+ * and every column index of such a row must lie in the same range (checked).
+ * Result per problem i is identical (up to rounding order) to sketchycgal_init
+ * + step on that problem alone with params.instance + i.
+ * Limits: q_t <= 128 for every problem and t; n_i >= R;
+ * sum of n_i < 2^31.  Conventions as for the single-problem entry points.
+ * ---------------------------------------------------------------------- */
+typedef struct scg_batch scg_batch;
+
+/* Workspace bytes for problems of sizes inst_n[0..n_inst) with nnz stored
+ * entries in total (diagonals included). */
+scg_status scg_batch_workspace_size(const scg_params* p, int32_t n_inst, const int64_t* inst_n,
+                                    int64_t nnz, size_t* bytes);
+
+/* Initialise every problem (alg:sketchy-cgal, Init):
+ *   inst_n   host int64[n_inst], sizes n_i >= R
+ *   row_ptr  device int64[N+1] (N = sum n_i), as in sketchycgal_init
+ *   col      device int32[nnz], global column numbers inside the row's block
+ *   val, b   device double[nnz], double[N], finite
+ *   workspace device, scg_batch_workspace_size bytes, 256-byte aligned, owned
+ *            by the caller until sketchycgal_batch_destroy
+ *   stream   hipStream_t; on a non-null stream step() replays captured HIP
+ *            graphs of 16 iterations, on the null stream it launches eagerly
+ * The value format (values, or columns only when all off-diagonal entries
+ * of all problems share one value / one magnitude) is chosen once for the
+ * batch.  Synchronises.  Errors as sketchycgal_init. */
+scg_status sketchycgal_batch_init(scg_batch** out, const scg_params* p, int32_t n_inst,
+                                  const int64_t* inst_n, int64_t nnz, const int64_t* row_ptr,
+                                  const int32_t* col, const double* val, const double* b,
+                                  void* workspace, size_t ws_bytes, void* stream);
+
+/* Enqueue `iters` iterations for every problem; asynchronous.  SCG_ESTATE
+ * past T. */
+scg_status sketchycgal_batch_step(scg_batch* ctx, int32_t iters);
+
+/* Per-problem iteration records, summary (original units), checkpoint state
+ * (z, y device double[n_i]; S device double[n_i*R] row-major; any pointer of
+ * get_state may be NULL; set_state puts problem `inst` at iteration t_next,
+ * 1 <= t_next <= T+1, and step() then requires every problem to have `iters`
+ * iterations left) and reconstruction (U device double[n_i*R] column-major,
+ * lambda and err device double[R]; as sketchycgal_reconstruct).  All
+ * synchronise. */
+scg_status sketchycgal_batch_log(scg_batch* ctx, int32_t inst, scg_iter_log* host_out, int32_t max,
+                                 int32_t* count);
+scg_status sketchycgal_batch_summary(scg_batch* ctx, int32_t inst, scg_summary* host_out);
+scg_status sketchycgal_batch_get_state(scg_batch* ctx, int32_t inst, int32_t* t_next, double* z,
+                                       double* y, double* S, double* p, double* tau);
+scg_status sketchycgal_batch_set_state(scg_batch* ctx, int32_t inst, int32_t t_next, const double* z,
+                                       const double* y, const double* S, double p, double tau);
+scg_status sketchycgal_batch_reconstruct(scg_batch* ctx, int32_t inst, double* U, double* lambda,
+                                         double* err);
+void sketchycgal_batch_destroy(scg_batch* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,9 @@ EXPORTS = [
     "sketchycgal_reconstruct", "sketchycgal_log", "sketchycgal_summary", "sketchycgal_get_state",
     "sketchycgal_set_state", "sketchycgal_lanczos_coeffs", "sketchycgal_apply", "sketchycgal_time_spmv",
     "sketchycgal_destroy", "scg_status_string",
+    "scg_batch_workspace_size", "sketchycgal_batch_init", "sketchycgal_batch_step", "sketchycgal_batch_log",
+    "sketchycgal_batch_summary", "sketchycgal_batch_get_state", "sketchycgal_batch_set_state", "sketchycgal_batch_reconstruct",
+    "sketchycgal_batch_destroy",
 ]
 
 _lib = None
@@ -75,6 +78,16 @@ def load() -> C.CDLL:
     lib.sketchycgal_time_spmv.argtypes = [vp, i32, P(C.c_double)]
     lib.sketchycgal_destroy.argtypes = [vp]
     lib.sketchycgal_destroy.restype = None
+    lib.scg_batch_workspace_size.argtypes = [P(scg_params), i32, vp, i64, P(sz)]
+    lib.sketchycgal_batch_init.argtypes = [P(vp), P(scg_params), i32, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    lib.sketchycgal_batch_step.argtypes = [vp, i32]
+    lib.sketchycgal_batch_log.argtypes = [vp, i32, P(scg_iter_log), i32, P(i32)]
+    lib.sketchycgal_batch_summary.argtypes = [vp, i32, P(scg_summary)]
+    lib.sketchycgal_batch_get_state.argtypes = [vp, i32, P(i32), vp, vp, vp, P(C.c_double), P(C.c_double)]
+    lib.sketchycgal_batch_set_state.argtypes = [vp, i32, i32, vp, vp, vp, C.c_double, C.c_double]
+    lib.sketchycgal_batch_reconstruct.argtypes = [vp, i32, vp, vp, vp]
+    lib.sketchycgal_batch_destroy.argtypes = [vp]
+    lib.sketchycgal_batch_destroy.restype = None
     lib.scg_status_string.argtypes = [C.c_int]
     lib.scg_status_string.restype = C.c_char_p
     for name in EXPORTS:

@@ -171,3 +171,117 @@ class SketchyCGAL:
         ms = C.c_double()
         check(self.lib.sketchycgal_time_spmv(self.ctx, reps, C.byref(ms)), "sketchycgal_time_spmv")
         return ms.value
+
+
+def batch_workspace_bytes(params: Params, inst_n, nnz: int) -> int:
+    lib = _lib.load()
+    ns = np.ascontiguousarray(np.asarray(inst_n, dtype=np.int64))
+    out = C.c_size_t()
+    check(lib.scg_batch_workspace_size(C.byref(params.to_c()), len(ns), ns.ctypes.data, int(nnz), C.byref(out)),
+          "scg_batch_workspace_size")
+    return out.value
+
+
+class BatchedSketchyCGAL:
+    """Many independent instances advanced together, one launch per iteration.
+
+    `instances` is a sequence of objects with row_ptr, col, val, b (numpy, CSR
+    with instance-local column numbers); they are concatenated into one
+    block-diagonal CSR here.  Instance i draws its random streams with Philox
+    counter word params.instance + i.  A private non-default stream is used so
+    that runs of iterations replay a captured HIP graph.
+    """
+
+    def __init__(self, instances, params: Params, device="cuda:0", stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.params = params
+        ns = np.array([int(len(g.b)) for g in instances], dtype=np.int64)
+        offs = np.concatenate([[0], np.cumsum(ns)])
+        nnzs = np.array([int(g.row_ptr[-1]) for g in instances], dtype=np.int64)
+        eoffs = np.concatenate([[0], np.cumsum(nnzs)])
+        rp = np.concatenate([np.asarray(g.row_ptr[:-1], dtype=np.int64) + eoffs[i] for i, g in enumerate(instances)]
+                            + [np.array([eoffs[-1]], dtype=np.int64)])
+        cl = np.concatenate([np.asarray(g.col, dtype=np.int64) + offs[i] for i, g in enumerate(instances)])
+        vl = np.concatenate([np.asarray(g.val, dtype=np.float64) for g in instances])
+        bb = np.concatenate([np.asarray(g.b, dtype=np.float64) for g in instances])
+        self.inst_n = ns
+        self.n_inst = len(ns)
+        self.nnz = int(eoffs[-1])
+        nbytes = batch_workspace_bytes(params, ns, self.nnz)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        d_rp = _dev(rp, torch.int64, self.device)
+        d_cl = _dev(cl.astype(np.int32), torch.int32, self.device)
+        d_vl = _dev(vl, torch.float64, self.device)
+        d_b = _dev(bb, torch.float64, self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        self.ctx = C.c_void_p()
+        cp = params.to_c()
+        st = self.lib.sketchycgal_batch_init(C.byref(self.ctx), C.byref(cp), self.n_inst, ns.ctypes.data, self.nnz,
+                                             _ptr(d_rp), _ptr(d_cl), _ptr(d_vl), _ptr(d_b), base + off, nbytes,
+                                             self.stream.cuda_stream)
+        check(st, "sketchycgal_batch_init")
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self.lib.sketchycgal_batch_destroy(ctx)
+            self.ctx = None
+
+    def step(self, iters: int = 1):
+        check(self.lib.sketchycgal_batch_step(self.ctx, iters), "sketchycgal_batch_step")
+
+    def run(self, iters: int | None = None):
+        self.step(self.params.T if iters is None else iters)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def log(self, inst: int) -> dict:
+        cap = self.params.T
+        arr = (_lib.scg_iter_log * cap)()
+        cnt = C.c_int32()
+        check(self.lib.sketchycgal_batch_log(self.ctx, inst, arr, cap, C.byref(cnt)), "sketchycgal_batch_log")
+        return {name: np.array([getattr(arr[i], name) for i in range(cnt.value)])
+                for name, _ in _lib.scg_iter_log._fields_}
+
+    def summary(self, inst: int, check_numeric: bool = True) -> dict:
+        s = _lib.scg_summary()
+        st = self.lib.sketchycgal_batch_summary(self.ctx, inst, C.byref(s))
+        if check_numeric:
+            check(st, "sketchycgal_batch_summary")
+        return {name: getattr(s, name) for name, _ in _lib.scg_summary._fields_}
+
+    def get_state(self, inst: int):
+        n = int(self.inst_n[inst])
+        R = self.params.R
+        z = torch.empty(n, dtype=torch.float64, device=self.device)
+        y = torch.empty_like(z)
+        S = torch.empty(n * R, dtype=torch.float64, device=self.device)
+        t = C.c_int32()
+        p = C.c_double()
+        tau = C.c_double()
+        check(self.lib.sketchycgal_batch_get_state(self.ctx, inst, C.byref(t), _ptr(z), _ptr(y), _ptr(S),
+                                                   C.byref(p), C.byref(tau)), "sketchycgal_batch_get_state")
+        return {"t": t.value, "z": z, "y": y, "S": S.view(n, R), "p": p.value, "tau": tau.value}
+
+    def set_state(self, inst: int, t, z, y, S, p, tau):
+        z = _dev(z, torch.float64, self.device)
+        y = _dev(y, torch.float64, self.device)
+        S = _dev(S, torch.float64, self.device).reshape(-1)
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.sketchycgal_batch_set_state(self.ctx, inst, int(t), _ptr(z), _ptr(y), _ptr(S), float(p),
+                                                   float(tau)), "sketchycgal_batch_set_state")
+
+    def reconstruct(self, inst: int):
+        n = int(self.inst_n[inst])
+        R = self.params.R
+        U = torch.empty(R * n, dtype=torch.float64, device=self.device)
+        lam = torch.empty(R, dtype=torch.float64, device=self.device)
+        err = torch.empty(R, dtype=torch.float64, device=self.device)
+        check(self.lib.sketchycgal_batch_reconstruct(self.ctx, inst, _ptr(U), _ptr(lam), _ptr(err)),
+              "sketchycgal_batch_reconstruct")
+        return U.view(R, n).t(), lam, err

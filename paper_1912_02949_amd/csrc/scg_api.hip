@@ -75,7 +75,7 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.part = take(8 * (size_t)kGMax * pw);
     L.counter = take(256);
     L.logs = take(sizeof(scg_iter_log) * (size_t)p.T);
-    L.recon_bytes = 8 * (n * R + 256 * 3 * (size_t)kRMax * kRMax + 11 * (size_t)kRMax * kRMax + 64);
+    L.recon_bytes = 8 * scg_recon_scratch_doubles(n, p.R);
     L.recon = take(L.recon_bytes);
     L.total = off;
     return L;

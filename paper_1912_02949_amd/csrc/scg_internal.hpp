@@ -126,3 +126,21 @@ struct scg_ctx {
     double* recon;   // reconstruction scratch (n x R FP64 and small matrices)
     size_t recon_bytes;
 };
+
+// Arguments of the FP64 Nystrom reconstruction of one sketch (column-major
+// S and Omega with column stride ld, storage type by fp32).
+struct ReconArgs {
+    int64_t n, ld;
+    int R, fp32, trace_correct;
+    const void* S;
+    const void* Om;
+    double tau, alpha;
+    double* scratch;      // scg_recon_scratch_doubles(n, R) doubles
+    unsigned* counter;    // zeroed ticket word
+    hipStream_t stream;
+    double* U;            // n x R column-major (stride n)
+    double* lambda;       // R
+    double* err;          // R or NULL
+};
+size_t scg_recon_scratch_doubles(int64_t n, int R);
+scg_status scg_reconstruct_generic(const ReconArgs& a);

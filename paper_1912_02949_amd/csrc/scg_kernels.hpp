@@ -526,6 +526,9 @@ __global__ __launch_bounds__(kBlock) void k_ritz(Prob<T> P) {
             for (int i = 0; i < 4; ++i) a[i] += cj * t[i];
         }
         st4(P.v + r, m, a);
+        // norm and v^T Omega of the stored (rounded) vector, which every later step uses
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = (double)(T)a[i];
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[0] += a[i] * a[i];
 #pragma unroll

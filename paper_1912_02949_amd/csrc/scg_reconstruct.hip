@@ -365,45 +365,66 @@ __global__ __launch_bounds__(kBlock) void k_out(int64_t n, int R, const double* 
 }
 
 template <typename T>
-scg_status recon_typed(scg_ctx* c, double* U, double* lambda, double* err) {
-    const int64_t n = c->n;
-    const int R = c->prm.R;
+scg_status recon_generic(const ReconArgs& a) {
+    const int64_t n = a.n;
+    const int R = a.R;
     const Small L = small_layout(R);
-    double* A = c->recon;                                  // n x R, FP64
-    double* part = c->recon + (size_t)n * R;               // kGR x 3 R^2
+    double* A = a.scratch;                                  // n x R, FP64
+    double* part = a.scratch + (size_t)n * R;               // kGR x 3 R^2
     double* small = part + (size_t)kGR * 3 * kRMax * kRMax;
-    const int fp32 = (c->prm.precision == SCG_FP32_STREAM);
-    const T* S = (const T*)c->S;
-    const T* Om = (const T*)c->Om;
+    const T* S = (const T*)a.S;
+    const T* Om = (const T*)a.Om;
     const dim3 g(kGR), b(kBlock);
-    hipLaunchKernelGGL((k_gram0<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, part, c->counter, small, L);
-    hipLaunchKernelGGL(k_small_sigma, dim3(1), dim3(64), 0, c->stream, n, R, fp32, small, L);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, A, 1, small, L, L.Lc, part, c->counter);
-    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, c->stream, n, R, small, L, L.L1, 1);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, A, 0, small, L, L.L1, part, c->counter);
-    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, c->stream, n, R, small, L, L.L2, 0);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, c->stream, n, c->ld, R, S, Om, A, 0, small, L, L.L2, part, c->counter);
-    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, c->stream, n, R, small, L, L.L3, 0);
-    // tau of the sketch (scaled units)
-    DevScalars hsc;
-    if (hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-        return SCG_EHIP;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return SCG_EHIP;
-    hipLaunchKernelGGL(k_small_svd, dim3(1), dim3(64), 0, c->stream, R, small, L, hsc.tau, c->alpha_s,
-                       c->prm.trace_correct, lambda, err);
+    hipStream_t st = a.stream;
+    hipLaunchKernelGGL((k_gram0<T>), g, b, 0, st, n, a.ld, R, S, Om, part, a.counter, small, L);
+    hipLaunchKernelGGL(k_small_sigma, dim3(1), dim3(64), 0, st, n, R, a.fp32, small, L);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, A, 1, small, L, L.Lc, part, a.counter);
+    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, st, n, R, small, L, L.L1, 1);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, A, 0, small, L, L.L1, part, a.counter);
+    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, st, n, R, small, L, L.L2, 0);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, A, 0, small, L, L.L2, part, a.counter);
+    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, st, n, R, small, L, L.L3, 0);
+    hipLaunchKernelGGL(k_small_svd, dim3(1), dim3(64), 0, st, R, small, L, a.tau, a.alpha, a.trace_correct, a.lambda,
+                       a.err);
     const int go = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(k_out, dim3(go), b, 0, c->stream, n, R, A, small, L, U);
+    hipLaunchKernelGGL(k_out, dim3(go), b, 0, st, n, R, A, small, L, a.U);
     if (hipGetLastError() != hipSuccess) return SCG_EHIP;
-    double st[2];
-    if (hipMemcpyAsync(st, small + L.scal, sizeof(st), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-        return SCG_EHIP;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return SCG_EHIP;
-    return (st[1] != 0.0) ? SCG_ENUMERIC : SCG_OK;
+    double stt[2];
+    if (hipMemcpyAsync(stt, small + L.scal, sizeof(stt), hipMemcpyDeviceToHost, st) != hipSuccess) return SCG_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SCG_EHIP;
+    return (stt[1] != 0.0) ? SCG_ENUMERIC : SCG_OK;
 }
 
 }  // namespace
 
+size_t scg_recon_scratch_doubles(int64_t n, int R) {
+    return (size_t)n * R + (size_t)kGR * 3 * kRMax * kRMax + 11 * (size_t)kRMax * kRMax + 64;
+}
+
+scg_status scg_reconstruct_generic(const ReconArgs& a) {
+    return a.fp32 ? recon_generic<float>(a) : recon_generic<double>(a);
+}
+
 scg_status scg_reconstruct_impl(scg_ctx* c, double* U, double* lambda, double* err) {
-    if (c->prm.precision == SCG_FP32_STREAM) return recon_typed<float>(c, U, lambda, err);
-    return recon_typed<double>(c, U, lambda, err);
+    DevScalars hsc;
+    if (hipMemcpyAsync(&hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return SCG_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SCG_EHIP;
+    ReconArgs a;
+    a.n = c->n;
+    a.ld = c->ld;
+    a.R = c->prm.R;
+    a.fp32 = (c->prm.precision == SCG_FP32_STREAM);
+    a.S = c->S;
+    a.Om = c->Om;
+    a.tau = hsc.tau;
+    a.alpha = c->alpha_s;
+    a.trace_correct = c->prm.trace_correct;
+    a.scratch = c->recon;
+    a.counter = c->counter;
+    a.stream = c->stream;
+    a.U = U;
+    a.lambda = lambda;
+    a.err = err;
+    return scg_reconstruct_generic(a);
 }

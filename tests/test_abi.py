@@ -74,3 +74,45 @@ def test_init_rejects_null_and_misaligned_arguments():
     assert ctx.value is None
     assert lib.sketchycgal_step(None, 1) == _lib.SCG_EINVAL
     assert lib.scg_status_string(_lib.SCG_ENOMEM) == b"workspace too small"
+
+
+def _bws(sizes, nnz=1000, **kw):
+    import numpy as np
+    lib = _lib.load()
+    p = _lib.scg_params()
+    lib.scg_default_params(C.byref(p))
+    p.R = 8
+    for k, v in kw.items():
+        setattr(p, k, v)
+    ns = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+    out = C.c_size_t()
+    return lib.scg_batch_workspace_size(C.byref(p), len(ns), ns.ctypes.data, nnz, C.byref(out)), out.value
+
+
+def test_batch_workspace_size_and_validation():
+    st, b = _bws([200, 5000, 20000])
+    assert st == _lib.SCG_OK and b > 0
+    st2, b2 = _bws([200, 5000, 20000], precision=_lib.SCG_FP32_STREAM)
+    assert st2 == _lib.SCG_OK and b2 < b
+    st3, b3 = _bws([200, 5000, 20000, 300])
+    assert st3 == _lib.SCG_OK and b3 > b
+    for sizes, kw in [([200, 5], {}), ([], {}), ([100], dict(reorth=1)), ([100], dict(T=0)),
+                      ([1000], dict(q_mode=1, q_fixed=129)), ([100], dict(precision=3)), ([100], dict(R=33))]:
+        st, _ = _bws(sizes, **kw)
+        assert st == _lib.SCG_EINVAL, (sizes, kw)
+
+
+def test_batch_init_rejects_null_and_misaligned_arguments():
+    import numpy as np
+    lib = _lib.load()
+    p = _lib.scg_params()
+    lib.scg_default_params(C.byref(p))
+    p.R = 8
+    ns = np.array([100, 200], dtype=np.int64)
+    ctx = C.c_void_p()
+    assert lib.sketchycgal_batch_init(C.byref(ctx), C.byref(p), 2, ns.ctypes.data, 900, None, None, None, None,
+                                      None, 0, None) == _lib.SCG_EINVAL
+    assert lib.sketchycgal_batch_init(C.byref(ctx), C.byref(p), 2, ns.ctypes.data, 900, 8, 8, 8, 8, 12345,
+                                      1 << 30, None) == _lib.SCG_EINVAL
+    assert ctx.value is None
+    assert lib.sketchycgal_batch_step(None, 1) == _lib.SCG_EINVAL
