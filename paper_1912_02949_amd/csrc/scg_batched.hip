@@ -38,7 +38,8 @@ constexpr int kBW = kBT / 64;       // waves
 constexpr int kQB = 128;            // Lanczos steps per call
 constexpr int kGraphChunk = 16;     // iterations per captured graph
 constexpr int kRedMax = kRMax + 1;  // widest workgroup reduction
-constexpr size_t kXLBytes = 128 * 1024;   // LDS for the vector being multiplied
+constexpr int kLongRow = 64;        // rows with more off-diagonal entries are summed by a whole wave
+constexpr size_t kLdsBudget = 136 * 1024;   // dynamic LDS: the vector being multiplied + slice table
 
 // LDS slots of the workgroup reduction results
 enum : int {
@@ -50,12 +51,16 @@ enum : int {
 };
 
 struct BatchInst {
-    int64_t row0;      // first row in the concatenated numbering
+    int64_t row0;      // first row in the concatenated CSR numbering
+    int64_t pos0;      // offset of the instance's vectors (a multiple of 64 elements)
     int64_t off_V;     // element offset of the instance's Lanczos basis
     int64_t off_OS;    // element offset of the instance's Omega and S
     int64_t ld;        // column stride of its basis, Omega, S (n rounded up to 64)
+    int64_t sl0;       // first entry of its slices in the slice table
     int n;
     int id;            // Philox counter word of the instance
+    int nshort;        // rows stored in slices; the remaining n - nshort rows are long
+    int nsl;           // slices
     double cval;       // common off-diagonal value / magnitude, scaled (compressed formats)
     double alpha_s;    // alpha in scaled units
     double c_F, alpha; // scaling constants
@@ -72,9 +77,10 @@ struct BatchArgs {
     BatchScal* scal;
     const int32_t* order;
     const int32_t* qtab;    // q_t per instance: qtab[i * T + t - 1]
-    const int32_t* rp;      // off-diagonal row pointers, concatenated rows
+    const int32_t* rp;      // off-diagonal row pointers, concatenated rows (at row0)
     const CT* col;          // instance-local column (sign in the top bit for FMT_SGN)
     const T* val;
+    // per-instance vectors at pos0
     const double* dC;
     const double* b;
     double* z;
@@ -86,6 +92,14 @@ struct BatchArgs {
     const T* Om;
     T* S;
     scg_iter_log* logs;     // logs[i * T + t - 1]
+    // sliced layout (LDS path): positions are short rows by decreasing length, then long rows
+    const int32_t* perm;    // position -> local row (at pos0)
+    T* s_pos;               // shift in position order (at pos0)
+    const double* dC_pos;   // diagonal of C in position order (at pos0)
+    const int2* sdesc;      // slice table: element offset of the slice, width (even)
+    const CT* scol;         // slice entries: pair p of lane l at offset + 2 (64 p + l)
+    const T* sval;
+    int desc_lds_off;       // byte offset of the slice table in dynamic LDS
     int T_iters;
     int R;
     int reorth;             // 2: Gram-Schmidt pass against the whole basis
@@ -115,6 +129,21 @@ __device__ __forceinline__ void breduce(const double (&v)[N], double* red, doubl
     __syncthreads();
 }
 
+// rows (or positions) of quad qd that exist: 4, or fewer in the tail quad
+__device__ __forceinline__ int quad_m(int qd, int n) {
+    const int r = 4 * qd;
+    return (r >= n) ? 0 : ((n - r >= 4) ? 4 : n - r);
+}
+__device__ __forceinline__ void ldi4(const int32_t* p, int m, int (&o)[4]) {
+    if (m == 4) {
+        const int4 t = *reinterpret_cast<const int4*>(p);
+        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = (j < m) ? p[j] : 0;
+    }
+}
+
 template <typename CT>
 __device__ __forceinline__ int col_index(CT cw) {
     if (sizeof(CT) == 2) return (int)((unsigned)cw & 0x7fffu);
@@ -126,14 +155,18 @@ __device__ __forceinline__ bool col_neg(CT cw) {
     return (int32_t)cw < 0;
 }
 
-// Nonzero e of the off-diagonal part times x (the common value of the
-// compressed formats is applied once per row by the caller).
+// Off-diagonal entry (column word cw, value vv) times x; the common value of
+// the compressed formats is applied once per row by the caller.
 template <typename T, typename CT, int FMT>
-__device__ __forceinline__ T nz(CT cw, const T* val, int e, const T* x) {
-    if (FMT == FMT_VAL) return val[e] * x[(int)cw];
+__device__ __forceinline__ T nzv(CT cw, T vv, const T* x) {
+    if (FMT == FMT_VAL) return vv * x[(int)cw];
     if (FMT == FMT_PAT) return x[(int)cw];
     const T xv = x[col_index(cw)];
     return col_neg(cw) ? -xv : xv;
+}
+template <typename T, typename CT, int FMT>
+__device__ __forceinline__ T nz(CT cw, const T* val, int e, const T* x) {
+    return nzv<T, CT, FMT>(cw, (FMT == FMT_VAL) ? val[e] : (T)0, x);
 }
 
 // sum_{e in row} C_e x_col(e), four nonzeros in flight per step.
@@ -151,206 +184,136 @@ __device__ __forceinline__ T row_product(const int32_t* rp, const CT* col, const
     return a0 + a1;
 }
 
-// One whole iteration of alg:sketchy-cgal for the instance of this workgroup.
-// XL: the vector being multiplied is kept in LDS (dynamic shared memory of
-// ld * sizeof(T) bytes), so the SpMV gathers never leave the CU.
-template <typename T, typename CT, int FMT, int RB, bool XL>
-__global__ __launch_bounds__(kBT) void k_batch_iter(BatchArgs<T, CT> A) {
-    extern __shared__ __align__(16) unsigned char dyn_lds[];
-    __shared__ double red[kRedMax * kBW];
-    __shared__ double so[SO_N];
-    __shared__ double s_inv[kQB + 1], s_coef[kQB], s_h[kQB + 8];
-    __shared__ double td[kQB], te[kQB], te2[kQB], tdp[kQB], tdm[kQB], tx[kQB];
-    __shared__ double s_xi;
-    T* xl = reinterpret_cast<T*>(dyn_lds);
-    const int ii = A.order[blockIdx.x];
-    const BatchInst D = A.inst[ii];
-    BatchScal* G = A.scal + ii;
-    const int t = G->t_next;
-    if (t > A.T_iters) return;
+// Two consecutive slice entries of one lane, loaded as one word and split on use.
+template <typename CT> struct PairW;
+template <> struct PairW<uint16_t> { using type = uint32_t; };
+template <> struct PairW<int32_t> { using type = int2; };
+template <typename CT>
+__device__ __forceinline__ typename PairW<CT>::type load_cw(const CT* p) {
+    return *reinterpret_cast<const typename PairW<CT>::type*>(p);
+}
+__device__ __forceinline__ uint16_t pair_lo(uint32_t w) { return (uint16_t)(w & 0xffffu); }
+__device__ __forceinline__ uint16_t pair_hi(uint32_t w) { return (uint16_t)(w >> 16); }
+__device__ __forceinline__ int32_t pair_lo(int2 w) { return w.x; }
+__device__ __forceinline__ int32_t pair_hi(int2 w) { return w.y; }
+template <typename T> struct PairV;
+template <> struct PairV<float> { using type = float2; };
+template <> struct PairV<double> { using type = double2; };
+
+// Row products over the sliced layout, the vector in LDS (xl, with xl[n] = 0
+// for the padding entries).  Wave w owns slices w, w + 16, ...; four of them
+// (their entries, rows, shifts and, for the objective, diagonals) are loaded
+// before any is consumed.  `fin(p, row, a, shift, diag)` receives each row's
+// off-diagonal sum (without the common value of the compressed formats).
+template <typename T, typename CT, int FMT, bool OBJ, typename Fin>
+__device__ __forceinline__ void sell_product(const int2* desc, int nsl, int nshort, int n, const int32_t* perm,
+                                             const T* sp, const double* dCp, const CT* scol, const T* sval,
+                                             const int32_t* rp, const CT* col, const T* val, const T* xl, Fin fin) {
+    using PW = typename PairW<CT>::type;
+    using PV = typename PairV<T>::type;
+    constexpr int PF = (sizeof(CT) == 2 && FMT != FMT_VAL) ? 6 : 4;   // pairs loaded ahead per slice
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int kb = wv; kb < nsl; kb += 4 * kBW) {
+        int2 d[4];
+        int row[4];
+        T sv[4];
+        double dg[4];
+        PW cw[4][PF];
+        PV vw[4][(FMT == FMT_VAL) ? PF : 1];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int k = kb + g * kBW;
+            d[g] = (k < nsl) ? desc[k] : make_int2(0, 0);
+            const int p = k * 64 + lane;
+            const bool ok = (k < nsl) && (p < nshort);
+            row[g] = ok ? perm[p] : -1;
+            sv[g] = ok ? sp[p] : (T)0;
+            dg[g] = (OBJ && ok) ? dCp[p] : 0.0;
+#pragma unroll
+            for (int pp = 0; pp < PF; ++pp) {
+                const size_t o = (size_t)d[g].x + 2 * (size_t)(pp * 64 + lane);
+                if (2 * pp < d[g].y) {
+                    cw[g][pp] = load_cw(scol + o);
+                    if (FMT == FMT_VAL) vw[g][pp] = *reinterpret_cast<const PV*>(sval + o);
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            T a = 0;
+#pragma unroll
+            for (int pp = 0; pp < PF; ++pp) {
+                if (2 * pp < d[g].y) {
+                    const T v0 = (FMT == FMT_VAL) ? (T)vw[g][pp].x : (T)0;
+                    const T v1 = (FMT == FMT_VAL) ? (T)vw[g][pp].y : (T)0;
+                    a += nzv<T, CT, FMT>((CT)pair_lo(cw[g][pp]), v0, xl) + nzv<T, CT, FMT>((CT)pair_hi(cw[g][pp]), v1, xl);
+                }
+            }
+            for (int pp = PF; 2 * pp < d[g].y; ++pp) {   // wide slices
+                const size_t o = (size_t)d[g].x + 2 * (size_t)(pp * 64 + lane);
+                const PW w = load_cw(scol + o);
+                T v0 = 0, v1 = 0;
+                if (FMT == FMT_VAL) {
+                    const PV vv = *reinterpret_cast<const PV*>(sval + o);
+                    v0 = vv.x;
+                    v1 = vv.y;
+                }
+                a += nzv<T, CT, FMT>((CT)pair_lo(w), v0, xl) + nzv<T, CT, FMT>((CT)pair_hi(w), v1, xl);
+            }
+            if (row[g] >= 0) fin((kb + g * kBW) * 64 + lane, row[g], (double)a, (double)sv[g], dg[g]);
+        }
+    }
+    // long rows: one wave each
+    for (int p = nshort + wv; p < n; p += kBW) {
+        const int r = perm[p];
+        const int e0 = rp[r], e1 = rp[r + 1];
+        T a = 0;
+        for (int e = e0 + lane; e < e1; e += 64) a += nz<T, CT, FMT>(col[e], val, e, xl);
+        const double tot = wave_sum((double)a);
+        if (lane == 0) fin(p, r, tot, (double)sp[p], OBJ ? dCp[p] : 0.0);
+    }
+}
+
+// Shared end of an iteration (the objective products are already in
+// so[SO_OBJ], so[SO_OBJ + 1]; the Ritz vector is vget(r) and v_hat = v iv):
+// primal update of z, the dual step size (eqn sketchy-cgal-dual-step) with
+// the K guard, the dual and sketch updates, the trackers and the record.
+template <typename T, typename CT, typename VG>
+__device__ __forceinline__ void iteration_tail(const BatchArgs<T, CT>& A, const BatchInst& D, BatchScal* G, int ii,
+                                               int t, int q, int k, double xi, double beta, double eta, double iv,
+                                               double vnorm2, VG vget, double* red, double* so) {
+    const int tid = threadIdx.x;
     const int n = D.n;
     const int64_t ld = D.ld;
-    const int tid = threadIdx.x;
-    const int q = A.qtab[(size_t)ii * A.T_iters + (t - 1)];
-    const double beta = A.beta0 * sqrt(t + 1.0);
-    const double eta = 2.0 / (t + 1.0);
     const double alpha = D.alpha_s;
-    const double cv = (FMT == FMT_VAL) ? 1.0 : D.cval;
-    const int32_t* rp = A.rp + D.row0;
-    double* z = A.z + D.row0;
-    double* y = A.y + D.row0;
-    const double* b = A.b + D.row0;
-    const double* dC = A.dC + D.row0;
-    T* s = A.s + D.row0;
-    T* u = A.u + D.row0;
-    T* v = A.v + D.row0;
-    T* V = A.V + D.off_V;
-    const T* Om = A.Om + D.off_OS;
+    double* z = A.z + D.pos0;
+    double* y = A.y + D.pos0;
+    const double* b = A.b + D.pos0;
     T* S = A.S + D.off_OS;
     const int R = A.R;
-
-    // shift s = dC + y + beta (z - b), start vector, state dot products
-    {
-        double a[6] = {0, 0, 0, 0, 0, 0};
-        for (int qd = tid; 4 * qd < n; qd += kBT) {
-            double g[4];
-            normal4(A.seed, (uint64_t)qd, (uint64_t)t, (uint64_t)D.id, 0ull, g);
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int r = 4 * qd + m;
-                if (r < n) {
-                    const double zr = z[r], yr = y[r], br = b[r];
-                    const double zb = zr - br;
-                    s[r] = (T)(dC[r] + (yr + beta * zb));
-                    const T gt = (T)g[m];
-                    V[r] = gt;
-                    if (XL) xl[r] = gt;
-                    a[0] += g[m] * g[m];
-                    a[1] += yr * br;
-                    a[2] += zb * (zr + br);
-                    a[3] += (yr + beta * zb) * zr;
-                    a[4] += zb * zb;
-                    a[5] += br * br;
-                }
-            }
-        }
-        breduce<6>(a, red, so + SO_PREP);
-    }
-    if (tid == 0) s_inv[0] = 1.0 / sqrt(so[SO_PREP]);
-    __syncthreads();
-
-    // randomized Lanczos (alg:rand-lanczos); the basis is stored unnormalised
-    int k = 0;
-    double rho_prev = 0.0;
-    for (int i = 0; i < q; ++i) {
-        T* x = V + (size_t)i * ld;
-        const T* xg = XL ? xl : x;
-        const double xs = s_inv[i];
-        double acc[1] = {0.0};
-        for (int r = tid; r < n; r += kBT) {
-            const T a = row_product<T, CT, FMT>(rp, A.col, A.val, r, xg);
-            const double xr = (double)xg[r];
-            const T ut = (T)(((double)a * cv + (double)s[r] * xr) * xs);
-            u[r] = ut;
-            acc[0] += xr * xs * (double)ut;
-        }
-        breduce<1>(acc, red, so + SO_OM);
-        const double om = so[SO_OM];
-        if (tid == 0) {
-            td[i] = om;
-            if (!isfinite(om)) G->flags |= 2;
-        }
-        k = i + 1;
-        if (i == q - 1) break;
-        const T* vm = (i > 0) ? V + (size_t)(i - 1) * ld : x;
-        T* w = V + (size_t)(i + 1) * ld;
-        const double c1 = om * xs, c2 = (i > 0) ? rho_prev * s_inv[i - 1] : 0.0;
-        double acc2[1] = {0.0};
-        for (int r = tid; r < n; r += kBT) {
-            const T wt = (T)((double)u[r] - c1 * (double)xg[r] - c2 * (double)vm[r]);
-            w[r] = wt;
-            if (XL) xl[r] = wt;   // own row: no other thread reads it before the barrier
-            acc2[0] += (double)wt * (double)wt;
-        }
-        if (A.reorth == 2) {
-            // h_j = v_hat_j^T w for j <= i, eight at a time, then w <- w - sum_j h_j v_hat_j
-            for (int jb = 0; jb <= i; jb += 8) {
-                double hacc[8];
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) hacc[jj] = 0.0;
-                for (int r = tid; r < n; r += kBT) {
-                    const double wr = (double)w[r];
-#pragma unroll
-                    for (int jj = 0; jj < 8; ++jj)
-                        if (jb + jj <= i) hacc[jj] += (double)V[(size_t)(jb + jj) * ld + r] * wr;
-                }
-                breduce<8>(hacc, red, s_h + jb);
-            }
-            acc2[0] = 0.0;
-            for (int r = tid; r < n; r += kBT) {
-                double a = 0.0;
-                for (int j = 0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + r];
-                const T wt = (T)((double)w[r] - a);
-                w[r] = wt;
-                if (XL) xl[r] = wt;
-                acc2[0] += (double)wt * (double)wt;
-            }
-        }
-        breduce<1>(acc2, red, so + SO_RHO);
-        const double rho = sqrt(so[SO_RHO]);
-        if (!(rho > 64.0 * DBL_EPSILON * (fabs(om) + rho_prev))) {   // breakdown
-            if (tid == 0) G->flags |= isfinite(rho) ? 1 : 3;
-            break;
-        }
-        if (tid == 0) {
-            te[i] = rho;
-            s_inv[i + 1] = 1.0 / rho;
-        }
-        rho_prev = rho;
-        __syncthreads();
-    }
-    __syncthreads();
-
-    // MinEvec of T_k on wave 0, then the Ritz coefficients
-    if (tid < 64) tridiag_min_eig(td, te, k, te2, tdp, tdm, tx, &s_xi);
-    __syncthreads();
-    for (int i = tid; i < k; i += kBT) s_coef[i] = tx[i] * s_inv[i];
-    __syncthreads();
-    const double xi = s_xi;
-
-    // Ritz vector v = sum_j coef_j V_j, ||v||^2 and v^T Omega
-    {
-        double racc[RB + 1];
-#pragma unroll
-        for (int c = 0; c <= RB; ++c) racc[c] = 0.0;
-        for (int r = tid; r < n; r += kBT) {
-            double a = 0.0;
-            for (int j = 0; j < k; ++j) a += s_coef[j] * (double)V[(size_t)j * ld + r];
-            const T vt = (T)a;
-            v[r] = vt;
-            if (XL) xl[r] = vt;
-            const double vr = (double)vt;   // the stored value is the one every later step uses
-            racc[0] += vr * vr;
-#pragma unroll
-            for (int c = 0; c < RB; ++c)
-                if (c < R) racc[c + 1] += vr * (double)Om[(size_t)c * ld + r];
-        }
-        breduce<RB + 1>(racc, red, so + SO_RITZ);
-    }
-    const double vnorm2 = so[SO_RITZ];
-    const double iv = 1.0 / sqrt(vnorm2);
-    const T* vg = XL ? xl : v;
-
-    // objective v_hat^T C v_hat and the eigen-residual ||D v_hat - xi v_hat||^2
-    {
-        double oa[2] = {0.0, 0.0};
-        for (int r = tid; r < n; r += kBT) {
-            const T a = row_product<T, CT, FMT>(rp, A.col, A.val, r, vg);
-            const double xr = (double)vg[r] * iv;
-            const double off = (double)a * cv * iv;
-            const double cvr = off + dC[r] * xr;
-            const double rr = (off + (double)s[r] * xr) - xi * xr;
-            oa[0] += xr * cvr;
-            oa[1] += rr * rr;
-        }
-        breduce<2>(oa, red, so + SO_OBJ);
-    }
-
-    // primal update z <- (1 - eta) z + eta alpha v_hat^2, ||z - b||^2
     const double ea = eta * alpha, keep = 1.0 - eta;
     const bool guard = isfinite(A.K);
     {
         double pa[3] = {0.0, 0.0, 0.0};
-        for (int r = tid; r < n; r += kBT) {
-            const double vh = (double)vg[r] * iv;
-            const double zn = keep * z[r] + ea * (vh * vh);
-            z[r] = zn;
-            const double dd = zn - b[r];
-            pa[0] += dd * dd;
-            if (guard) {
-                pa[1] += y[r] * y[r];
-                pa[2] += y[r] * dd;
+        for (int qd = tid; 4 * qd < n; qd += kBT) {
+            const int m = quad_m(qd, n), r = 4 * qd;
+            double z4[4], b4[4], y4[4];
+            ld4(z + r, m, z4);
+            ld4(b + r, m, b4);
+            if (guard) ld4(y + r, m, y4);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double vh = (j < m) ? vget(r + j) * iv : 0.0;
+                z4[j] = keep * z4[j] + ea * (vh * vh);
+                const double dd = (j < m) ? z4[j] - b4[j] : 0.0;
+                pa[0] += dd * dd;
+                if (guard) {
+                    pa[1] += y4[j] * y4[j];
+                    pa[2] += y4[j] * dd;
+                }
             }
+            st4(z + r, m, z4);
         }
         breduce<3>(pa, red, so + SO_PRIM);
     }
@@ -360,13 +323,31 @@ __global__ __launch_bounds__(kBT) void k_batch_iter(BatchArgs<T, CT> A) {
         const double ny2 = so[SO_PRIM + 1] + 2.0 * gamma * so[SO_PRIM + 2] + gamma * gamma * r2;
         if (sqrt(fmax(ny2, 0.0)) > A.K) gamma = 0.0;
     }
-    // dual update y <- y + gamma (z - b); sketch S <- (1 - eta) S + eta alpha v_hat (v_hat^T Omega)
-    for (int r = tid; r < n; r += kBT) {
-        y[r] += gamma * (z[r] - b[r]);
-        const double vh = ea * ((double)vg[r] * iv);
-        for (int c = 0; c < R; ++c) {
-            T* sp = S + (size_t)c * ld + r;
-            *sp = (T)(keep * (double)*sp + vh * (so[SO_RITZ + 1 + c] * iv));
+    for (int qd = tid; 4 * qd < n; qd += kBT) {
+        const int m = quad_m(qd, n), r = 4 * qd;
+        double y4[4], z4[4], b4[4], vh[4];
+        ld4(y + r, m, y4);
+        ld4(z + r, m, z4);
+        ld4(b + r, m, b4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            y4[j] += gamma * (z4[j] - b4[j]);
+            vh[j] = (j < m) ? ea * (vget(r + j) * iv) : 0.0;
+        }
+        st4(y + r, m, y4);
+        for (int c0 = 0; c0 < R; c0 += 4) {
+            double s4[4][4];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+                if (c0 + cc < R) ld4(S + (size_t)(c0 + cc) * ld + r, m, s4[cc]);
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+                if (c0 + cc < R) {
+                    const double cwv = so[SO_RITZ + 1 + c0 + cc] * iv;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) s4[cc][j] = keep * s4[cc][j] + vh[j] * cwv;
+                    st4(S + (size_t)(c0 + cc) * ld + r, m, s4[cc]);
+                }
         }
     }
     if (tid == 0) {
@@ -397,6 +378,424 @@ __global__ __launch_bounds__(kBT) void k_batch_iter(BatchArgs<T, CT> A) {
         if (!isfinite(p_new) || !isfinite(r2) || !isfinite(xi)) G->flags |= 2;
         G->t_next = t + 1;
     }
+}
+
+// Shift s = dC + y + beta (z - b) (primitive 2), the Lanczos start vector of
+// iteration t (handed to `put(r, g)`), and the state dot products used by the
+// gap and stopping quantities.
+template <typename T, typename CT, typename PUT>
+__device__ __forceinline__ void prep_shift(const BatchArgs<T, CT>& A, const BatchInst& D, int t, double beta, PUT put,
+                                           double* red, double* so) {
+    const int n = D.n;
+    const double* z = A.z + D.pos0;
+    const double* y = A.y + D.pos0;
+    const double* b = A.b + D.pos0;
+    const double* dC = A.dC + D.pos0;
+    T* s = A.s + D.pos0;
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    for (int qd = threadIdx.x; 4 * qd < n; qd += kBT) {
+        const int m = quad_m(qd, n), r = 4 * qd;
+        double g[4], z4[4], y4[4], b4[4], d4[4], s4[4];
+        normal4(A.seed, (uint64_t)qd, (uint64_t)t, (uint64_t)D.id, 0ull, g);
+        ld4(z + r, m, z4);
+        ld4(y + r, m, y4);
+        ld4(b + r, m, b4);
+        ld4(dC + r, m, d4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double zb = z4[j] - b4[j];
+            s4[j] = d4[j] + (y4[j] + beta * zb);
+            if (j < m) {
+                a[1] += y4[j] * b4[j];
+                a[2] += zb * (z4[j] + b4[j]);
+                a[3] += (y4[j] + beta * zb) * z4[j];
+                a[4] += zb * zb;
+                a[5] += b4[j] * b4[j];
+            } else {
+                g[j] = 0.0;
+            }
+            a[0] += g[j] * g[j];
+        }
+        st4(s + r, m, s4);
+        put(r, m, g);
+    }
+    breduce<6>(a, red, so + SO_PREP);
+}
+
+// One whole iteration of alg:sketchy-cgal for the instance of this workgroup,
+// the vector being multiplied in LDS.  The off-diagonal part is stored in
+// slices of 64 rows (rows sorted by length, padded to the slice's even
+// width); only the products use that order, every vector stays in row order.
+// Row loops move 4 consecutive entries per thread with 16-byte accesses.
+template <typename T, typename CT, int FMT, int RB>
+__global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    __shared__ double red[kRedMax * kBW];
+    __shared__ double so[SO_N];
+    __shared__ double s_inv[kQB + 1], s_coef[kQB], s_h[kQB + 8];
+    __shared__ double td[kQB], te[kQB], te2[kQB], tdp[kQB], tdm[kQB], tx[kQB];
+    __shared__ double s_xi;
+    T* xl = reinterpret_cast<T*>(dyn_lds);
+    int2* desc = reinterpret_cast<int2*>(dyn_lds + A.desc_lds_off);
+    const int ii = A.order[blockIdx.x];
+    const BatchInst D = A.inst[ii];
+    BatchScal* G = A.scal + ii;
+    const int t = G->t_next;
+    if (t > A.T_iters) return;
+    const int n = D.n, nshort = D.nshort, nsl = D.nsl;
+    const int64_t ld = D.ld;
+    const int tid = threadIdx.x;
+    const int q = A.qtab[(size_t)ii * A.T_iters + (t - 1)];
+    const double beta = A.beta0 * sqrt(t + 1.0);
+    const double eta = 2.0 / (t + 1.0);
+    const double cv = (FMT == FMT_VAL) ? 1.0 : D.cval;
+    const int32_t* rp = A.rp + D.row0;
+    const int32_t* perm = A.perm + D.pos0;
+    const T* s = A.s + D.pos0;
+    T* sp = A.s_pos + D.pos0;
+    const double* dCp = A.dC_pos + D.pos0;
+    T* u = A.u + D.pos0;
+    T* V = A.V + D.off_V;
+    const T* Om = A.Om + D.off_OS;
+    for (int kk = tid; kk < nsl; kk += kBT) desc[kk] = A.sdesc[D.sl0 + kk];
+    if (tid == 0) xl[n] = (T)0;
+
+    prep_shift<T, CT>(A, D, t, beta, [&](int r, int m, double (&g)[4]) {
+        st4(V + r, m, g);   // rounds g to the stored type
+        for (int j = 0; j < m; ++j) xl[r + j] = (T)g[j];
+    }, red, so);
+    // the shift in position order, for the products
+    for (int qd = tid; 4 * qd < n; qd += kBT) {
+        const int m = quad_m(qd, n), p = 4 * qd;
+        int rr[4];
+        ldi4(perm + p, m, rr);
+        double s4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s4[j] = (j < m) ? (double)s[rr[j]] : 0.0;
+        st4(sp + p, m, s4);
+    }
+    if (tid == 0) s_inv[0] = 1.0 / sqrt(so[SO_PREP]);
+    __syncthreads();
+
+    // randomized Lanczos (alg:rand-lanczos); the basis is stored unnormalised
+    int k = 0;
+    double rho_prev = 0.0;
+    for (int i = 0; i < q; ++i) {
+        const double xs = s_inv[i];
+        double acc[1] = {0.0};
+        sell_product<T, CT, FMT, false>(desc, nsl, nshort, n, perm, sp, dCp, A.scol, A.sval, rp, A.col, A.val, xl,
+                                        [&](int, int r, double a, double sv, double) {
+                                            const double xr = (double)xl[r];
+                                            const T ut = (T)((a * cv + sv * xr) * xs);
+                                            u[r] = ut;
+                                            acc[0] += xr * xs * (double)ut;
+                                        });
+        breduce<1>(acc, red, so + SO_OM);
+        const double om = so[SO_OM];
+        if (tid == 0) {
+            td[i] = om;
+            if (!isfinite(om)) G->flags |= 2;
+        }
+        k = i + 1;
+        if (i == q - 1) break;
+        const T* vm = V + (size_t)(i > 0 ? i - 1 : i) * ld;
+        T* w = V + (size_t)(i + 1) * ld;
+        const double c1 = om * xs, c2 = (i > 0) ? rho_prev * s_inv[i - 1] : 0.0;
+        double acc2[1] = {0.0};
+        for (int qb = tid; 4 * qb < n; qb += 2 * kBT) {
+            int mq[2];
+            double uu[2][4], mm[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int qd = qb + h * kBT;
+                mq[h] = quad_m(qd, n);
+                if (mq[h] > 0) {
+                    ld4(u + 4 * qd, mq[h], uu[h]);
+                    ld4(vm + 4 * qd, mq[h], mm[h]);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (mq[h] > 0) {
+                    const int r = 4 * (qb + h * kBT);
+                    double w4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        w4[j] = (j < mq[h]) ? uu[h][j] - c1 * (double)xl[r + j] - c2 * mm[h][j] : 0.0;
+                    st4(w + r, mq[h], w4);   // rounds w4 to the stored type
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (j < mq[h]) {
+                            xl[r + j] = (T)w4[j];   // own rows: no other thread reads them before the barrier
+                            acc2[0] += w4[j] * w4[j];
+                        }
+                }
+            }
+        }
+        if (A.reorth == 2) {
+            __syncthreads();   // w was written quad-wise by other threads
+            // h_j = v_hat_j^T w for j <= i, eight at a time, then w <- w - sum_j h_j v_hat_j
+            for (int jb = 0; jb <= i; jb += 8) {
+                double hacc[8];
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) hacc[jj] = 0.0;
+                for (int p = tid; p < n; p += kBT) {
+                    const double wr = (double)w[p];
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj)
+                        if (jb + jj <= i) hacc[jj] += (double)V[(size_t)(jb + jj) * ld + p] * wr;
+                }
+                breduce<8>(hacc, red, s_h + jb);
+            }
+            acc2[0] = 0.0;
+            for (int p = tid; p < n; p += kBT) {
+                double a = 0.0;
+                for (int j = 0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + p];
+                const T wt = (T)((double)w[p] - a);
+                w[p] = wt;
+                xl[p] = wt;
+                acc2[0] += (double)wt * (double)wt;
+            }
+        }
+        breduce<1>(acc2, red, so + SO_RHO);
+        const double rho = sqrt(so[SO_RHO]);
+        if (!(rho > 64.0 * DBL_EPSILON * (fabs(om) + rho_prev))) {   // breakdown
+            if (tid == 0) G->flags |= isfinite(rho) ? 1 : 3;
+            break;
+        }
+        if (tid == 0) {
+            te[i] = rho;
+            s_inv[i + 1] = 1.0 / rho;
+        }
+        rho_prev = rho;
+        __syncthreads();
+    }
+    __syncthreads();
+
+    // MinEvec of T_k on wave 0, then the Ritz coefficients
+    if (tid < 64) tridiag_min_eig(td, te, k, te2, tdp, tdm, tx, &s_xi);
+    __syncthreads();
+    for (int i = tid; i < k; i += kBT) s_coef[i] = tx[i] * s_inv[i];
+    __syncthreads();
+    const double xi = s_xi;
+
+    // Ritz vector v = sum_j coef_j V_j into LDS: basis column outer, four quads
+    // of rows per thread, two columns in flight
+    for (int qb0 = 0; 4 * qb0 < n; qb0 += 4 * kBT) {
+        double a4[4][4];
+        int mq[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            mq[h] = quad_m(qb0 + tid + h * kBT, n);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a4[h][j] = 0.0;
+        }
+#pragma unroll 2
+        for (int j = 0; j < k; ++j) {
+            const double cj = s_coef[j];
+            const T* Vj = V + (size_t)j * ld + 4 * (qb0 + tid);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                if (mq[h] > 0) {
+                    double t4[4];
+                    ld4(Vj + 4 * h * kBT, mq[h], t4);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) a4[h][jj] += cj * t4[jj];
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int r = 4 * (qb0 + tid + h * kBT);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < mq[h]) xl[r + j] = (T)a4[h][j];
+        }
+    }
+    __syncthreads();
+    // ||v||^2 and v^T Omega from the stored (rounded) vector
+    {
+        double racc[RB + 1];
+#pragma unroll
+        for (int c = 0; c <= RB; ++c) racc[c] = 0.0;
+        for (int qd = tid; 4 * qd < n; qd += kBT) {
+            const int m = quad_m(qd, n), r = 4 * qd;
+            double v4[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v4[j] = (j < m) ? (double)xl[r + j] : 0.0;
+                racc[0] += v4[j] * v4[j];
+            }
+#pragma unroll
+            for (int c = 0; c < RB; ++c)
+                if (c < A.R) {
+                    double o4[4];
+                    ld4(Om + (size_t)c * ld + r, m, o4);
+                    racc[c + 1] += v4[0] * o4[0] + v4[1] * o4[1] + v4[2] * o4[2] + v4[3] * o4[3];
+                }
+        }
+        breduce<RB + 1>(racc, red, so + SO_RITZ);
+    }
+    const double vnorm2 = so[SO_RITZ];
+    const double iv = 1.0 / sqrt(vnorm2);
+
+    // objective v_hat^T C v_hat and the eigen-residual ||D v_hat - xi v_hat||^2
+    {
+        double oa[2] = {0.0, 0.0};
+        sell_product<T, CT, FMT, true>(desc, nsl, nshort, n, perm, sp, dCp, A.scol, A.sval, rp, A.col, A.val, xl,
+                                       [&](int p, int r, double a, double sv, double dg) {
+                                           const double xr = (double)xl[r] * iv;
+                                           const double off = a * cv * iv;
+                                           const double rr = (off + sv * xr) - xi * xr;
+                                           oa[0] += xr * (off + dg * xr);
+                                           oa[1] += rr * rr;
+                                       });
+        breduce<2>(oa, red, so + SO_OBJ);
+    }
+    iteration_tail<T, CT>(A, D, G, ii, t, q, k, xi, beta, eta, iv, vnorm2, [&](int r) { return (double)xl[r]; },
+                          red, so);
+}
+
+// The same iteration with the SpMV gathering from global memory (instances
+// whose vector does not fit the LDS budget): CSR rows in row order, one
+// thread per row.
+template <typename T, typename CT, int FMT, int RB>
+__global__ __launch_bounds__(kBT) void k_batch_iter(BatchArgs<T, CT> A) {
+    __shared__ double red[kRedMax * kBW];
+    __shared__ double so[SO_N];
+    __shared__ double s_inv[kQB + 1], s_coef[kQB], s_h[kQB + 8];
+    __shared__ double td[kQB], te[kQB], te2[kQB], tdp[kQB], tdm[kQB], tx[kQB];
+    __shared__ double s_xi;
+    const int ii = A.order[blockIdx.x];
+    const BatchInst D = A.inst[ii];
+    BatchScal* G = A.scal + ii;
+    const int t = G->t_next;
+    if (t > A.T_iters) return;
+    const int n = D.n;
+    const int64_t ld = D.ld;
+    const int tid = threadIdx.x;
+    const int q = A.qtab[(size_t)ii * A.T_iters + (t - 1)];
+    const double beta = A.beta0 * sqrt(t + 1.0);
+    const double eta = 2.0 / (t + 1.0);
+    const double cv = (FMT == FMT_VAL) ? 1.0 : D.cval;
+    const int32_t* rp = A.rp + D.row0;
+    const double* dC = A.dC + D.pos0;
+    T* s = A.s + D.pos0;
+    T* u = A.u + D.pos0;
+    T* v = A.v + D.pos0;
+    T* V = A.V + D.off_V;
+    const T* Om = A.Om + D.off_OS;
+
+    prep_shift<T, CT>(A, D, t, beta, [&](int r, int m, double (&g)[4]) { st4(V + r, m, g); }, red, so);
+    if (tid == 0) s_inv[0] = 1.0 / sqrt(so[SO_PREP]);
+    __syncthreads();
+
+    int k = 0;
+    double rho_prev = 0.0;
+    for (int i = 0; i < q; ++i) {
+        T* x = V + (size_t)i * ld;
+        const double xs = s_inv[i];
+        double acc[1] = {0.0};
+        for (int r = tid; r < n; r += kBT) {
+            const T a = row_product<T, CT, FMT>(rp, A.col, A.val, r, x);
+            const double xr = (double)x[r];
+            const T ut = (T)(((double)a * cv + (double)s[r] * xr) * xs);
+            u[r] = ut;
+            acc[0] += xr * xs * (double)ut;
+        }
+        breduce<1>(acc, red, so + SO_OM);
+        const double om = so[SO_OM];
+        if (tid == 0) {
+            td[i] = om;
+            if (!isfinite(om)) G->flags |= 2;
+        }
+        k = i + 1;
+        if (i == q - 1) break;
+        const T* vm = (i > 0) ? V + (size_t)(i - 1) * ld : x;
+        T* w = V + (size_t)(i + 1) * ld;
+        const double c1 = om * xs, c2 = (i > 0) ? rho_prev * s_inv[i - 1] : 0.0;
+        double acc2[1] = {0.0};
+        for (int r = tid; r < n; r += kBT) {
+            const T wt = (T)((double)u[r] - c1 * (double)x[r] - c2 * (double)vm[r]);
+            w[r] = wt;
+            acc2[0] += (double)wt * (double)wt;
+        }
+        if (A.reorth == 2) {
+            for (int jb = 0; jb <= i; jb += 8) {
+                double hacc[8];
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) hacc[jj] = 0.0;
+                for (int r = tid; r < n; r += kBT) {
+                    const double wr = (double)w[r];
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj)
+                        if (jb + jj <= i) hacc[jj] += (double)V[(size_t)(jb + jj) * ld + r] * wr;
+                }
+                breduce<8>(hacc, red, s_h + jb);
+            }
+            acc2[0] = 0.0;
+            for (int r = tid; r < n; r += kBT) {
+                double a = 0.0;
+                for (int j = 0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + r];
+                const T wt = (T)((double)w[r] - a);
+                w[r] = wt;
+                acc2[0] += (double)wt * (double)wt;
+            }
+        }
+        breduce<1>(acc2, red, so + SO_RHO);
+        const double rho = sqrt(so[SO_RHO]);
+        if (!(rho > 64.0 * DBL_EPSILON * (fabs(om) + rho_prev))) {   // breakdown
+            if (tid == 0) G->flags |= isfinite(rho) ? 1 : 3;
+            break;
+        }
+        if (tid == 0) {
+            te[i] = rho;
+            s_inv[i + 1] = 1.0 / rho;
+        }
+        rho_prev = rho;
+        __syncthreads();
+    }
+    __syncthreads();
+
+    if (tid < 64) tridiag_min_eig(td, te, k, te2, tdp, tdm, tx, &s_xi);
+    __syncthreads();
+    for (int i = tid; i < k; i += kBT) s_coef[i] = tx[i] * s_inv[i];
+    __syncthreads();
+    const double xi = s_xi;
+
+    {
+        double racc[RB + 1];
+#pragma unroll
+        for (int c = 0; c <= RB; ++c) racc[c] = 0.0;
+        for (int r = tid; r < n; r += kBT) {
+            double a = 0.0;
+            for (int j = 0; j < k; ++j) a += s_coef[j] * (double)V[(size_t)j * ld + r];
+            const T vt = (T)a;
+            v[r] = vt;
+            const double vr = (double)vt;   // the stored value is the one every later step uses
+            racc[0] += vr * vr;
+#pragma unroll
+            for (int c = 0; c < RB; ++c)
+                if (c < A.R) racc[c + 1] += vr * (double)Om[(size_t)c * ld + r];
+        }
+        breduce<RB + 1>(racc, red, so + SO_RITZ);
+    }
+    const double vnorm2 = so[SO_RITZ];
+    const double iv = 1.0 / sqrt(vnorm2);
+    {
+        double oa[2] = {0.0, 0.0};
+        for (int r = tid; r < n; r += kBT) {
+            const T a = row_product<T, CT, FMT>(rp, A.col, A.val, r, v);
+            const double xr = (double)v[r] * iv;
+            const double off = (double)a * cv * iv;
+            const double rr = (off + (double)s[r] * xr) - xi * xr;
+            oa[0] += xr * (off + dC[r] * xr);
+            oa[1] += rr * rr;
+        }
+        breduce<2>(oa, red, so + SO_OBJ);
+    }
+    iteration_tail<T, CT>(A, D, G, ii, t, q, k, xi, beta, eta, iv, vnorm2, [&](int r) { return (double)v[r]; },
+                          red, so);
 }
 
 // ---------------------------------------------------------------- init kernels
@@ -451,9 +850,9 @@ __global__ __launch_bounds__(256) void k_bvalidate(int64_t nrows, const int64_t*
 template <typename T, typename CT>
 __global__ __launch_bounds__(256) void k_bscatter(int64_t nrows, const int64_t* rp, const int32_t* col,
                                                   const double* val, const double* b_in, const int32_t* inst_of_row,
-                                                  const int64_t* row0, const double* inv_cF, const double* inv_alpha,
-                                                  const int32_t* rp_off, CT* col_off, T* val_off,
-                                                  const double* dCraw, double* dC, double* b_out, int fmt) {
+                                                  const int64_t* row0, const int64_t* pos0, const double* inv_cF,
+                                                  const double* inv_alpha, const int32_t* rp_off, CT* col_off,
+                                                  T* val_off, const double* dCraw, double* dC, double* b_out, int fmt) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
         const int k = inst_of_row[r];
         const int64_t base = row0[k];
@@ -474,8 +873,9 @@ __global__ __launch_bounds__(256) void k_bscatter(int64_t nrows, const int64_t* 
             }
             ++o;
         }
-        dC[r] = dCraw[r] * sc;
-        b_out[r] = b_in[r] * inv_alpha[k];
+        const int64_t pr = pos0[k] + (r - base);
+        dC[pr] = dCraw[r] * sc;
+        b_out[pr] = b_in[r] * inv_alpha[k];
     }
 }
 
@@ -519,26 +919,28 @@ int q_of(const scg_params& p, int64_t n, int t) {
 }
 
 struct BLayout {
-    size_t inst, scal, order, qtab, rp, col, val, dC, b, z, y, s, u, v, V, Om, S, logs, iorow, row0, ninst, invc, inva,
-        mm, err, recon, total;
-    int64_t nrows, Vtot, OStot;
+    size_t inst, scal, order, qtab, rp, col, val, dC, b, z, y, s, u, v, V, Om, S, logs, iorow, row0, pos0, ninst, invc,
+        inva, mm, err, recon, perm, s_pos, dC_pos, sdesc, scol, sval, total;
+    int64_t nrows, nvec, Vtot, OStot, sell_cap, nsl_cap;
 };
 
 BLayout blayout(const scg_params& p, int ninst, const int64_t* inst_n, int64_t nnz) {
     BLayout L{};
     const size_t es = (p.precision == SCG_FP32_STREAM) ? 4 : 8;
-    int64_t nrows = 0, Vtot = 0, OStot = 0, nmax = 0;
+    int64_t nrows = 0, nvec = 0, Vtot = 0, OStot = 0, nmax = 0;
     for (int k = 0; k < ninst; ++k) {
         const int64_t n = inst_n[k];
         const int64_t ld = (n + 63) / 64 * 64;
         int qm = 1;
         for (int t = 1; t <= p.T; ++t) qm = std::max(qm, q_of(p, n, t));
         nrows += n;
+        nvec += ld;
         Vtot += (int64_t)(qm + 1) * ld;
         OStot += (int64_t)p.R * ld;
         nmax = std::max(nmax, n);
     }
     L.nrows = nrows;
+    L.nvec = nvec;
     L.Vtot = Vtot;
     L.OStot = OStot;
     size_t off = 0;
@@ -550,25 +952,37 @@ BLayout blayout(const scg_params& p, int ninst, const int64_t* inst_n, int64_t n
     L.rp = take(4 * (size_t)(nrows + 1));
     L.col = take(4 * (size_t)nnz);
     L.val = take(es * (size_t)nnz);
-    L.dC = take(8 * nrows);
-    L.b = take(8 * nrows);
-    L.z = take(8 * nrows);
-    L.y = take(8 * nrows);
-    L.s = take(es * nrows);
-    L.u = take(es * nrows);
-    L.v = take(es * nrows);
+    // per-instance vectors at 64-aligned offsets pos0 (row order; perm, s_pos, dC_pos in slice position order)
+    L.dC = take(8 * nvec);
+    L.b = take(8 * nvec);
+    L.z = take(8 * nvec);
+    L.y = take(8 * nvec);
+    L.s = take(es * nvec);
+    L.u = take(es * nvec);
+    L.v = take(es * nvec);
     L.V = take(es * (size_t)Vtot);
     L.Om = take(es * (size_t)OStot);
     L.S = take(es * (size_t)OStot);
     L.logs = take(sizeof(scg_iter_log) * (size_t)ninst * p.T);
     L.iorow = take(4 * (size_t)nrows);
     L.row0 = take(8 * (size_t)ninst);
+    L.pos0 = take(8 * (size_t)ninst);
     L.ninst = take(4 * (size_t)ninst);
     L.invc = take(8 * (size_t)ninst);
     L.inva = take(8 * (size_t)ninst);
     L.mm = take(8 * 4 * (size_t)1024 * 16);
     L.err = take(512);   // validation flags, then the reconstruction's counter at +256
     L.recon = take(8 * scg_recon_scratch_doubles(nmax, p.R));
+    // sliced layout: padding is at most 64 * kLongRow per instance (rows sorted by length),
+    // plus one entry per row (even widths) and the last slice's unused lanes
+    L.sell_cap = nnz + nrows + (int64_t)ninst * (64 * kLongRow + 64 + 63 * kLongRow + 64);
+    L.nsl_cap = nrows / 64 + ninst;
+    L.perm = take(4 * (size_t)nvec);
+    L.s_pos = take(es * (size_t)nvec);
+    L.dC_pos = take(8 * (size_t)nvec);
+    L.sdesc = take(8 * (size_t)L.nsl_cap);
+    L.scol = take(4 * (size_t)L.sell_cap);
+    L.sval = take(es * (size_t)L.sell_cap);
     L.total = off;
     return L;
 }
@@ -578,12 +992,13 @@ BLayout blayout(const scg_params& p, int ninst, const int64_t* inst_n, int64_t n
 struct scg_batch {
     scg_params prm;
     int ninst;
-    int64_t nrows, nnz_in, nnz_off;
+    int64_t nrows, nvec, nnz_in, nnz_off;
     hipStream_t stream;
     int fmt;
     bool col16;        // 16-bit column indices (every instance small enough)
-    bool xl;           // the multiplied vector kept in LDS
-    size_t xl_bytes;   // dynamic LDS per workgroup when xl
+    bool xl;           // the multiplied vector kept in LDS (sliced-layout kernel)
+    size_t lds_bytes;  // dynamic LDS per workgroup when xl
+    int desc_lds_off;  // byte offset of the slice table in dynamic LDS
     std::vector<BatchInst> hinst;
     std::vector<int64_t> row0;
     BatchInst* inst;
@@ -598,6 +1013,12 @@ struct scg_batch {
     scg_iter_log* logs;
     double* recon;
     unsigned* counter;
+    int32_t* perm;
+    void* s_pos;
+    double* dC_pos;
+    int2* sdesc;
+    void* scol;
+    void* sval;
     std::vector<int> t_host;   // per-instance next iteration, mirrored on the host
     hipGraphExec_t graph;
     bool graph_ready;
@@ -626,6 +1047,13 @@ BatchArgs<T, CT> bargs(scg_batch* c) {
     A.Om = (const T*)c->Om;
     A.S = (T*)c->S;
     A.logs = c->logs;
+    A.perm = c->perm;
+    A.s_pos = (T*)c->s_pos;
+    A.dC_pos = c->dC_pos;
+    A.sdesc = c->sdesc;
+    A.scol = (const CT*)c->scol;
+    A.sval = (const T*)c->sval;
+    A.desc_lds_off = c->desc_lds_off;
     A.T_iters = c->prm.T;
     A.R = c->prm.R;
     A.reorth = c->prm.reorth;
@@ -636,21 +1064,24 @@ BatchArgs<T, CT> bargs(scg_batch* c) {
 }
 
 // Launch one iteration, or (prepare) raise the kernel's dynamic-LDS limit.
-template <typename T, typename CT, int FMT, int RB, bool XL>
+template <typename T, typename CT, int FMT, int RB>
 hipError_t launch_leaf(scg_batch* c, bool prepare) {
-    auto* kern = &k_batch_iter<T, CT, FMT, RB, XL>;
-    const unsigned lds = XL ? (unsigned)c->xl_bytes : 0u;
-    if (prepare) return XL ? hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                           : hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(c->ninst), dim3(kBT), lds, c->stream, bargs<T, CT>(c));
+    if (c->xl) {
+        auto* kern = &k_batch_sell<T, CT, FMT, RB>;
+        const unsigned lds = (unsigned)c->lds_bytes;
+        if (prepare) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(c->ninst), dim3(kBT), lds, c->stream, bargs<T, CT>(c));
+    } else {
+        if (prepare) return hipSuccess;
+        hipLaunchKernelGGL((k_batch_iter<T, CT, FMT, RB>), dim3(c->ninst), dim3(kBT), 0, c->stream, bargs<T, CT>(c));
+    }
     return hipGetLastError();
 }
 
 template <typename T, typename CT, int FMT>
 hipError_t launch_fmt(scg_batch* c, bool prepare) {
-    if (c->prm.R <= 8)
-        return c->xl ? launch_leaf<T, CT, FMT, 8, true>(c, prepare) : launch_leaf<T, CT, FMT, 8, false>(c, prepare);
-    return c->xl ? launch_leaf<T, CT, FMT, kRMax, true>(c, prepare) : launch_leaf<T, CT, FMT, kRMax, false>(c, prepare);
+    if (c->prm.R <= 8) return launch_leaf<T, CT, FMT, 8>(c, prepare);
+    return launch_leaf<T, CT, FMT, kRMax>(c, prepare);
 }
 
 template <typename T, typename CT>
@@ -667,6 +1098,74 @@ hipError_t launch_t(scg_batch* c, bool prepare) {
 
 hipError_t enqueue_iter(scg_batch* c, bool prepare = false) {
     return (c->prm.precision == SCG_FP32_STREAM) ? launch_t<float>(c, prepare) : launch_t<double>(c, prepare);
+}
+
+// Sliced layout of every instance's off-diagonal part (from the scattered CSR):
+// rows with at most kLongRow entries sorted by decreasing length (ties by row),
+// cut into slices of 64, each padded to its even maximum width with the index
+// n (x[n] = 0 in LDS; value 0); longer rows follow in row order and keep CSR.
+template <typename T, typename CT>
+scg_status build_slices(scg_batch* c, const BLayout& L, const std::vector<int32_t>& hrp_off) {
+    const int64_t nvec = c->nvec;
+    const int64_t nnz = c->nnz_off;
+    const bool vals = (c->fmt == FMT_VAL);
+    std::vector<CT> hcol(nnz);
+    std::vector<T> hval(vals ? nnz : 0);
+    std::vector<double> hdC(nvec);
+    if (nnz > 0) HIP_TRY(hipMemcpyAsync(hcol.data(), c->col, sizeof(CT) * nnz, hipMemcpyDeviceToHost, c->stream));
+    if (vals && nnz > 0) HIP_TRY(hipMemcpyAsync(hval.data(), c->val, sizeof(T) * nnz, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hdC.data(), c->dC, 8 * nvec, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> perm(nvec, 0);
+    std::vector<double> dCp(nvec, 0.0);
+    std::vector<int2> desc;
+    std::vector<CT> scol;
+    std::vector<T> sval;
+    for (int k = 0; k < c->ninst; ++k) {
+        BatchInst& I = c->hinst[k];
+        const int64_t r0 = I.row0;
+        const int n = I.n;
+        auto len = [&](int r) { return hrp_off[r0 + r + 1] - hrp_off[r0 + r]; };
+        std::vector<int32_t> order;
+        std::vector<int32_t> longs;
+        for (int r = 0; r < n; ++r) (len(r) <= kLongRow ? order : longs).push_back(r);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len(a) > len(b); });
+        I.nshort = (int)order.size();
+        I.nsl = (I.nshort + 63) / 64;
+        I.sl0 = (int64_t)desc.size();
+        order.insert(order.end(), longs.begin(), longs.end());
+        for (int p = 0; p < n; ++p) {
+            perm[I.pos0 + p] = order[p];
+            dCp[I.pos0 + p] = hdC[I.pos0 + order[p]];
+        }
+        for (int sl = 0; sl < I.nsl; ++sl) {
+            const int w = (len(order[64 * sl]) + 1) & ~1;
+            const int64_t off = (int64_t)scol.size();
+            desc.push_back(make_int2((int)off, w));
+            scol.resize(off + 64 * (int64_t)w, (CT)n);
+            if (vals) sval.resize(off + 64 * (int64_t)w, (T)0);
+            for (int l = 0; l < 64; ++l) {
+                const int p = 64 * sl + l;
+                if (p >= I.nshort) break;
+                const int r = order[p];
+                const int32_t e0 = hrp_off[r0 + r];
+                for (int j = 0; j < len(r); ++j) {
+                    const int64_t o = off + 2 * (int64_t)((j / 2) * 64 + l) + (j & 1);
+                    scol[o] = hcol[e0 + j];
+                    if (vals) sval[o] = hval[e0 + j];
+                }
+            }
+        }
+    }
+    if ((int64_t)scol.size() > L.sell_cap || (int64_t)desc.size() > L.nsl_cap || scol.size() > (size_t)INT32_MAX)
+        return SCG_EINVAL;
+    HIP_TRY(hipMemcpyAsync(c->perm, perm.data(), 4 * nvec, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->dC_pos, dCp.data(), 8 * nvec, hipMemcpyHostToDevice, c->stream));
+    if (!desc.empty()) HIP_TRY(hipMemcpyAsync(c->sdesc, desc.data(), 8 * desc.size(), hipMemcpyHostToDevice, c->stream));
+    if (!scol.empty()) HIP_TRY(hipMemcpyAsync(c->scol, scol.data(), sizeof(CT) * scol.size(), hipMemcpyHostToDevice, c->stream));
+    if (!sval.empty()) HIP_TRY(hipMemcpyAsync(c->sval, sval.data(), sizeof(T) * sval.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCG_OK;
 }
 
 template <typename T>
@@ -687,6 +1186,9 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     }
     int32_t* d_iorow = (int32_t*)(base + L.iorow);
     int64_t* d_row0 = (int64_t*)(base + L.row0);
+    int64_t* d_pos0 = (int64_t*)(base + L.pos0);
+    std::vector<int64_t> hpos0(ninst);
+    for (int k = 0; k < ninst; ++k) hpos0[k] = c->hinst[k].pos0;
     int* d_ninst = (int*)(base + L.ninst);
     double* d_invc = (double*)(base + L.invc);
     double* d_inva = (double*)(base + L.inva);
@@ -694,6 +1196,7 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     int* d_err = (int*)(base + L.err);
     HIP_TRY(hipMemcpyAsync(d_iorow, iorow.data(), 4 * nrows, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(d_row0, c->row0.data(), 8 * ninst, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(d_pos0, hpos0.data(), 8 * ninst, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(d_ninst, hn.data(), 4 * ninst, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(d_err, 0, 256, c->stream));
     int32_t* cnt = (int32_t*)(base + L.rp);   // scratch before the row pointers are written
@@ -730,10 +1233,17 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
         nmax = std::max<int64_t>(nmax, c->hinst[k].n);
         ldmax = std::max<int64_t>(ldmax, c->hinst[k].ld);
     }
-    // column words: 16 bits when every local index (and the sign bit) fits
-    c->col16 = (c->prm.matrix_format != 1) && (nmax <= ((c->fmt == FMT_SGN) ? 32768 : 65536));
-    c->xl_bytes = (size_t)ldmax * sizeof(T);
-    c->xl = c->xl_bytes <= kXLBytes;
+    // column words: 16 bits when every local index, the padding index n and the sign bit fit
+    c->col16 = (c->prm.matrix_format != 1) && (nmax <= ((c->fmt == FMT_SGN) ? 32767 : 65535));
+    // LDS path: the vector (plus the zero at index n) and the slice table fit the budget
+    {
+        int64_t nslmax = 0;
+        for (int k = 0; k < ninst; ++k) nslmax = std::max<int64_t>(nslmax, (c->hinst[k].n + 63) / 64);
+        const size_t xb = al256((size_t)(ldmax + 64) * sizeof(T));
+        c->desc_lds_off = (int)xb;
+        c->lds_bytes = xb + 8 * (size_t)nslmax;
+        c->xl = c->lds_bytes <= kLdsBudget;
+    }
     std::vector<double> invc(ninst), inva(ninst);
     for (int k = 0; k < ninst; ++k) {
         double ss = 0.0, sb = 0.0;
@@ -767,11 +1277,11 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     HIP_TRY(hipMemcpyAsync(d_inva, inva.data(), 8 * ninst, hipMemcpyHostToDevice, c->stream));
     if (c->col16)
         hipLaunchKernelGGL((k_bscatter<T, uint16_t>), dim3(gv), dim3(256), 0, c->stream, nrows, row_ptr, col, val, b,
-                           d_iorow, d_row0, d_invc, d_inva, c->rp, (uint16_t*)c->col, (T*)c->val, dCraw, c->dC, c->b,
+                           d_iorow, d_row0, d_pos0, d_invc, d_inva, c->rp, (uint16_t*)c->col, (T*)c->val, dCraw, c->dC, c->b,
                            c->fmt);
     else
         hipLaunchKernelGGL((k_bscatter<T, int32_t>), dim3(gv), dim3(256), 0, c->stream, nrows, row_ptr, col, val, b,
-                           d_iorow, d_row0, d_invc, d_inva, c->rp, (int32_t*)c->col, (T*)c->val, dCraw, c->dC, c->b,
+                           d_iorow, d_row0, d_pos0, d_invc, d_inva, c->rp, (int32_t*)c->col, (T*)c->val, dCraw, c->dC, c->b,
                            c->fmt);
     HIP_TRY(hipGetLastError());
     for (int k = 0; k < ninst; ++k) {
@@ -783,6 +1293,10 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));   // dCraw / sumsq consumed
+    if (c->xl) {
+        const scg_status st = c->col16 ? build_slices<T, uint16_t>(c, L, hrp_off) : build_slices<T, int32_t>(c, L, hrp_off);
+        if (st != SCG_OK) return st;
+    }
     // q schedule, LPT order, state
     std::vector<int32_t> qtab((size_t)ninst * c->prm.T);
     std::vector<double> work(ninst);
@@ -801,8 +1315,8 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     for (auto& x : hs) x.t_next = 1;
     HIP_TRY(hipMemcpyAsync(c->scal, hs.data(), sizeof(BatchScal) * ninst, hipMemcpyHostToDevice, c->stream));
     const size_t es = (c->prm.precision == SCG_FP32_STREAM) ? 4 : 8;
-    HIP_TRY(hipMemsetAsync(c->z, 0, 8 * nrows, c->stream));
-    HIP_TRY(hipMemsetAsync(c->y, 0, 8 * nrows, c->stream));
+    HIP_TRY(hipMemsetAsync(c->z, 0, 8 * c->nvec, c->stream));
+    HIP_TRY(hipMemsetAsync(c->y, 0, 8 * c->nvec, c->stream));
     HIP_TRY(hipMemsetAsync(c->S, 0, es * L.OStot, c->stream));
     HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * ninst * c->prm.T, c->stream));
     HIP_TRY(hipMemsetAsync(c->counter, 0, 256, c->stream));
@@ -856,6 +1370,7 @@ scg_status sketchycgal_batch_init(scg_batch** out, const scg_params* p, int32_t 
     c->prm = *p;
     c->ninst = n_inst;
     c->nrows = L.nrows;
+    c->nvec = L.nvec;
     c->nnz_in = nnz;
     c->stream = (hipStream_t)stream;
     c->graph = nullptr;
@@ -881,13 +1396,20 @@ scg_status sketchycgal_batch_init(scg_batch** out, const scg_params* p, int32_t 
     c->logs = (scg_iter_log*)(base + L.logs);
     c->recon = (double*)(base + L.recon);
     c->counter = (unsigned*)(base + L.err + 256);
+    c->perm = (int32_t*)(base + L.perm);
+    c->s_pos = base + L.s_pos;
+    c->dC_pos = (double*)(base + L.dC_pos);
+    c->sdesc = (int2*)(base + L.sdesc);
+    c->scol = base + L.scol;
+    c->sval = base + L.sval;
     c->hinst.resize(n_inst);
     c->row0.resize(n_inst);
-    int64_t r0 = 0, offV = 0, offOS = 0;
+    int64_t r0 = 0, offV = 0, offOS = 0, pv = 0;
     for (int k = 0; k < n_inst; ++k) {
         BatchInst& I = c->hinst[k];
         const int64_t n = inst_n[k];
         I.row0 = r0;
+        I.pos0 = pv;
         I.n = (int)n;
         I.id = p->instance + k;
         I.ld = (n + 63) / 64 * 64;
@@ -897,6 +1419,7 @@ scg_status sketchycgal_batch_init(scg_batch** out, const scg_params* p, int32_t 
         I.off_OS = offOS;
         c->row0[k] = r0;
         r0 += n;
+        pv += I.ld;
         offV += (int64_t)(qm + 1) * I.ld;
         offOS += (int64_t)p->R * I.ld;
     }
@@ -992,8 +1515,8 @@ scg_status sketchycgal_batch_get_state(scg_batch* c, int32_t inst, int32_t* t_ne
                                        double* p, double* tau) {
     if (!c || inst < 0 || inst >= c->ninst) return SCG_EINVAL;
     const BatchInst& I = c->hinst[inst];
-    if (z) HIP_TRY(hipMemcpyAsync(z, c->z + I.row0, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
-    if (y) HIP_TRY(hipMemcpyAsync(y, c->y + I.row0, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
+    if (z) HIP_TRY(hipMemcpyAsync(z, c->z + I.pos0, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
+    if (y) HIP_TRY(hipMemcpyAsync(y, c->y + I.pos0, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
     if (S) {
         if (c->prm.precision == SCG_FP32_STREAM)
             hipLaunchKernelGGL((k_bstate_out<float>), dim3(256), dim3(256), 0, c->stream, I.n, I.ld, c->prm.R,
@@ -1016,8 +1539,8 @@ scg_status sketchycgal_batch_set_state(scg_batch* c, int32_t inst, int32_t t_nex
     if (!c || inst < 0 || inst >= c->ninst || t_next < 1 || t_next > c->prm.T + 1 || !z || !y || !S)
         return SCG_EINVAL;
     const BatchInst& I = c->hinst[inst];
-    HIP_TRY(hipMemcpyAsync(c->z + I.row0, z, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->y + I.row0, y, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->z + I.pos0, z, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->y + I.pos0, y, 8 * I.n, hipMemcpyDeviceToDevice, c->stream));
     if (c->prm.precision == SCG_FP32_STREAM)
         hipLaunchKernelGGL((k_bstate_in<float>), dim3(256), dim3(256), 0, c->stream, I.n, I.ld, c->prm.R, S,
                            (float*)c->S + I.off_OS);
