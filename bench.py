@@ -9,11 +9,15 @@ reconstruction.  `value` is CGAL iterations per second of the FP32-stream
 form; the plain-FP64 form is timed beside it.
 
 Also reported:
+  batched       the batched form: 256 Erdos-Renyi instances (average degree 8,
+                n uniform in [200, 20000]), R = 8, T = 1000, all advanced by one
+                launch per iteration; instance-iterations per second, FP32 and FP64
   roofline      the Lanczos SpMV kernel: algorithmic bytes per launch over its
                 average duration (HIP events on the solver's stream) against
                 the MI355X HBM peak; `traffic` is the rocprofv3-measured HBM
-                bytes per launch when the committed counter summary matches
-                the current kernel source, else null
+                bytes per launch of the shape the autotuner chose (lanes per
+                row, workgroups), from the committed counter summary when it
+                matches the current kernel source, else null
   cpu_baseline  the FP64 oracle on this host's cores, on a bounded sample of
                 the same workload, extrapolated over the whole Lanczos schedule
 """
@@ -32,6 +36,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# SpMV shapes whose HBM traffic the profile records: (lanes per row, workgroups cap, column segments);
+# workgroups 0 = one row-block range per wave
+PROBE_SHAPES = tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_traffic_torus_1m_fp32.json")
 KERNEL_SOURCES = ["scg_kernels.hpp", "scg_device.hpp", "scg_internal.hpp"]
 
@@ -146,6 +153,39 @@ def cpu_baseline(inst, T: int, seconds: float = 15.0):
     }
 
 
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_leg(torch, T: int, with_fp64: bool):
+    """Whole batched solves (init excluded from the rate, reported beside it)."""
+    import synth
+    from paper_1912_02949_amd import BatchedSketchyCGAL, Params
+    insts = synth.batched_erdos_renyi(256, 200, 20000, 8)
+    out = {"workload": "256 MaxCut SDPs, Erdos-Renyi average degree 8, n uniform in [200, 20000] "
+                       "(sum n = %d), R=8, T=%d, q_t=ceil(t^(1/4) ln n_i)" % (sum(g.n for g in insts), T),
+           "instances": len(insts)}
+    for prec in (("fp32", "fp64") if with_fp64 else ("fp32",)):
+        prm = Params(R=8, T=T, seed=synth.CONFIG_SEEDS[4], precision=prec)
+        t0 = time.perf_counter()
+        b = BatchedSketchyCGAL(insts, prm)
+        b.synchronize()
+        t1 = time.perf_counter()
+        b.step(T)
+        b.synchronize()
+        t2 = time.perf_counter()
+        infeas = [b.summary(i)["infeasibility"] / math.sqrt(insts[i].n) for i in range(len(insts))]
+        out[prec] = {"batch_iters_per_s": T / (t2 - t1), "instance_iters_per_s": len(insts) * T / (t2 - t1),
+                     "ms_per_iteration": 1e3 * (t2 - t1) / T, "init_s": t1 - t0,
+                     "max_rel_infeasibility": max(infeas),
+                     "objective_sum": sum(b.summary(i)["objective"] for i in range(len(insts)))}
+        del b
+        progress(f"batched {prec}: {out[prec]['ms_per_iteration']:.3f} ms per iteration")
+    if with_fp64:
+        out["speedup_fp32_vs_fp64"] = out["fp32"]["batch_iters_per_s"] / out["fp64"]["batch_iters_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,9 +195,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-T", type=int, default=1000)
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="only the SpMV kernel leg (for rocprofv3 --pmc) plus a 256 MiB device copy whose "
-                         "counters calibrate FETCH_SIZE / WRITE_SIZE")
+                    help="only the SpMV kernel, 20 launches in each shape the autotuner chooses from (lanes per "
+                         "row x workgroups), for rocprofv3 --pmc, plus a 256 MiB device copy whose counters "
+                         "calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path is a design "
@@ -175,23 +218,32 @@ def main():
     p64 = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp64")
 
     if args.traffic_probe:
-        sp = Solve(inst, p32, torch)
-        sp.init()
-        sp.lib.sketchycgal_step(sp.ctx, 2)
-        ms = C.c_double()
-        sp.lib.sketchycgal_time_spmv(sp.ctx, 20, C.byref(ms))
-        sp.close()
+        shapes = []
+        for lanes, grid, seg in PROBE_SHAPES:
+            prm = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp32", autotune=0, segments=seg,
+                         spmv_lanes=lanes, spmv_grid=grid)
+            sp = Solve(inst, prm, torch)
+            sp.init()
+            sp.lib.sketchycgal_step(sp.ctx, 2)
+            ms = C.c_double()
+            sp.lib.sketchycgal_time_spmv(sp.ctx, 20, C.byref(ms))
+            summ = sp.summary()
+            sp.close()
+            shapes.append({"lanes": lanes, "workgroups": summ["spmv_grid"], "segments": summ["spmv_segments"],
+                           "spmv_avg_us": ms.value * 1e3, "lanczos_launches_before_timing": sum(qs[:2])})
+            progress(f"probe lanes={lanes} workgroups={summ['spmv_grid']} segments={seg}: {ms.value * 1e3:.1f} us")
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"spmv_avg_us": ms.value * 1e3, "copy_bytes": 4 * a.numel(),
+        print(json.dumps({"shapes": shapes, "copy_bytes": 4 * a.numel(),
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
         return
 
     s32 = Solve(inst, p32, torch)
     dt32 = timed(s32, args.steps, args.warmup, torch)
+    progress(f"fp32 solves: {1e3 * dt32 / args.steps:.1f} ms each")
     sum32 = s32.summary()
     # SpMV kernel leg: back-to-back launches on the solver's stream, HIP events
     ms = C.c_double()
@@ -206,17 +258,22 @@ def main():
     bytes_per_launch = per_nz * nnz_off + 4 * (n + 1) + 4 * n + 4 * n + 4 * n
     achieved = bytes_per_launch / (spmv_ms * 1e-3) / 1e9
 
+    # measured HBM bytes per launch of the shape the autotuner chose (same kernel source only)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha") == kernel_source_sha():
-            traffic = tr.get("hbm_bytes_per_launch")
+            for sh in tr.get("shapes", []):
+                if (sh["lanes"], sh["workgroups"], sh["segments"]) == (sum32["spmv_lanes"], sum32["spmv_grid"],
+                                                                       sum32["spmv_segments"]):
+                    traffic = sh["hbm_bytes_per_launch"]
 
     fp64 = None
     if not args.no_fp64:
         s64 = Solve(inst, p64, torch)
         dt64 = timed(s64, args.steps, args.warmup, torch)
+        progress(f"fp64 solves: {1e3 * dt64 / args.steps:.1f} ms each")
         sum64 = s64.summary()
         s64.close()
         fp64 = {
@@ -227,6 +284,7 @@ def main():
         }
     del s32
 
+    batched = None if args.no_batched else batched_leg(torch, args.batched_T, not args.no_fp64)
     cpu = None if args.no_cpu else cpu_baseline(inst, T, args.cpu_seconds)
 
     value = args.steps * T / dt32
@@ -260,10 +318,12 @@ def main():
             "avg_launch_us": spmv_ms * 1e3,
         },
         "spmv_tuning": {"lanes_per_row": sum32["spmv_lanes"], "column_segments": sum32["spmv_segments"],
+                        "workgroups": sum32["spmv_grid"],
                         "matrix_format": ["values", "columns only", "columns with sign bit"][sum32["matrix_format"]]},
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "result_fp32": {"objective": sum32["objective"], "infeasibility": sum32["infeasibility"]},
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -71,10 +71,14 @@ typedef struct {
     int32_t  instance;      /* Philox counter word selecting this problem's random streams   */
     int32_t  matrix_format; /* 0: compress the off-diagonal values when they share one
                                magnitude (columns only, sign in bit 31); 1: always store values */
-    int32_t  autotune;      /* 1: time the SpMV variants (lanes per row, column segments) at
-                               init and keep the fastest                                      */
+    int32_t  autotune;      /* 1: time the SpMV variants (lanes per row, column segments, grid
+                               size) at init and keep the fastest                             */
     int32_t  segments;      /* column segments of the SpMV: 0 = chosen by the autotuner
                                (1 below 1M nonzeros), or 1, 2, 4                              */
+    int32_t  spmv_lanes;    /* lanes per row of the SpMV reduction: 0 = autotuned / by mean
+                               row length, or 2, 4, 8, 16, 32                                 */
+    int32_t  spmv_grid;     /* SpMV workgroups: 0 = autotuned / one row-block range per wave,
+                               or a cap (rounded to a multiple of 8, at most 2048)            */
 } scg_params;
 
 /* One record per iteration t, in scaled units (see file comment).  Gap and
@@ -106,7 +110,7 @@ typedef struct {
     int32_t spmv_segments;    /* column segments of the SpMV                                   */
     int32_t matrix_format;    /* storage of the off-diagonal values: 0 values, 1 columns only
                                  (common value), 2 columns with sign bit (common magnitude)  */
-    int32_t pad;
+    int32_t spmv_grid;        /* workgroups of the SpMV launch                                 */
 } scg_summary;
 
 typedef struct scg_ctx scg_ctx;

@@ -17,7 +17,7 @@ class scg_params(C.Structure):
         ("alpha", C.c_double), ("seed", C.c_uint64), ("q_mode", C.c_int32), ("q_fixed", C.c_int32),
         ("scale", C.c_int32), ("trace_correct", C.c_int32), ("reorth", C.c_int32),
         ("precision", C.c_int32), ("instance", C.c_int32), ("matrix_format", C.c_int32),
-        ("autotune", C.c_int32), ("segments", C.c_int32),
+        ("autotune", C.c_int32), ("segments", C.c_int32), ("spmv_lanes", C.c_int32), ("spmv_grid", C.c_int32),
     ]
 
 
@@ -35,7 +35,7 @@ class scg_summary(C.Structure):
         ("t_done", C.c_int32), ("status_flags", C.c_int32), ("objective", C.c_double),
         ("infeasibility", C.c_double), ("p_scaled", C.c_double), ("tau_scaled", C.c_double),
         ("c_F", C.c_double), ("alpha", C.c_double), ("alpha_scaled", C.c_double),
-        ("spmv_lanes", C.c_int32), ("spmv_segments", C.c_int32), ("matrix_format", C.c_int32), ("pad", C.c_int32),
+        ("spmv_lanes", C.c_int32), ("spmv_segments", C.c_int32), ("matrix_format", C.c_int32), ("spmv_grid", C.c_int32),
     ]
 
 

@@ -35,6 +35,8 @@ class Params:
     matrix_format: int = 0        # 0: compress equal-magnitude off-diagonal values; 1: keep values
     autotune: int = 1
     segments: int = 0             # SpMV column segments: 0 auto, or 1, 2, 4
+    spmv_lanes: int = 0           # SpMV lanes per row: 0 auto, or 2, 4, 8, 16, 32
+    spmv_grid: int = 0            # SpMV workgroups: 0 auto, or a cap
 
     def to_c(self) -> _lib.scg_params:
         p = _lib.scg_params()
@@ -42,6 +44,7 @@ class Params:
         p.seed, p.q_mode, p.q_fixed, p.scale = self.seed, self.q_mode, self.q_fixed, self.scale
         p.trace_correct, p.reorth, p.instance = self.trace_correct, self.reorth, self.instance
         p.matrix_format, p.autotune, p.segments = self.matrix_format, self.autotune, self.segments
+        p.spmv_lanes, p.spmv_grid = self.spmv_lanes, self.spmv_grid
         p.precision = {"fp64": _lib.SCG_FP64, "fp32": _lib.SCG_FP32_STREAM}[self.precision]
         return p
 

@@ -499,7 +499,7 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
     HIP_TRY(hipEventCreate(&e1));
     const double mean = c->n > 0 ? (double)c->nnz_off / (double)c->n : 1.0;
     float best = 1e30f;
-    int best_l = c->lanes, best_s = 1;
+    int best_l = c->lanes, best_s = 1, best_g = 0;
     for (int nseg : {1, 2, 4}) {
         if (c->prm.segments > 0 && nseg != c->prm.segments) continue;
         if (nseg > 1) {
@@ -507,17 +507,27 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
             scg_status st = build_segments<T>(c, nseg, row_ptr, col, val);
             if (st != SCG_OK) return st;
         }
-        for (int l : {2, 4, 8, 16, 32}) {
-            if (l > 4 * mean + 4) break;
-            launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);   // warm-up
-            HIP_TRY(hipEventRecord(e0, c->stream));
-            for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);
-            HIP_TRY(hipEventRecord(e1, c->stream));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; best_l = l; best_s = nseg; }
+        // grid: one row-block range per wave (natural), or fewer workgroups so that
+        // the whole grid is resident and each wave walks a longer range
+        const int g_nat = c->Gs;
+        for (int gcap : {0, 1536, 1024}) {
+            if (c->prm.spmv_grid > 0 && gcap != 0) continue;   // a forced grid is applied afterwards
+            if (gcap != 0 && gcap >= g_nat) continue;
+            c->Gs = (gcap != 0) ? gcap : g_nat;
+            for (int l : {2, 4, 8, 16, 32}) {
+                if (c->prm.spmv_lanes > 0 && l != c->prm.spmv_lanes) continue;
+                if (c->prm.spmv_lanes == 0 && l > 4 * mean + 4) break;
+                launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);   // warm-up
+                HIP_TRY(hipEventRecord(e0, c->stream));
+                for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);
+                HIP_TRY(hipEventRecord(e1, c->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; best_l = l; best_s = nseg; best_g = gcap; }
+            }
         }
+        c->Gs = g_nat;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -525,6 +535,7 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         scg_status st = build_segments<T>(c, best_s, row_ptr, col, val);
         if (st != SCG_OK) return st;
     }
+    if (best_g != 0) c->Gs = std::min(c->Gs, best_g);
     c->lanes = best_l;
     return SCG_OK;
 }
@@ -629,6 +640,9 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
         scg_status st = build_segments<T>(c, c->prm.segments, row_ptr, col, val);
         if (st != SCG_OK) return st;
     }
+    // forced SpMV shape (overrides the autotuner)
+    if (c->prm.spmv_lanes > 0) c->lanes = c->prm.spmv_lanes;
+    if (c->prm.spmv_grid > 0) c->Gs = std::min(c->Gs, std::max(8, round8(c->prm.spmv_grid)));
     HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * c->prm.T, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->t_next = 1;
@@ -645,6 +659,9 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (p->reorth != 0 && p->reorth != 2) return false;
     if (p->precision != SCG_FP64 && p->precision != SCG_FP32_STREAM) return false;
     if (qmax_for(*p, n) + 1 > kQCap) return false;
+    const int l = p->spmv_lanes;
+    if (l != 0 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
+    if (p->spmv_grid < 0 || p->spmv_grid > kGMax) return false;
     return true;
 }
 
@@ -671,6 +688,8 @@ void scg_default_params(scg_params* p) {
     p->matrix_format = 0;
     p->autotune = 1;
     p->segments = 0;
+    p->spmv_lanes = 0;
+    p->spmv_grid = 0;
 }
 
 scg_status scg_workspace_size(const scg_params* p, int64_t n, int64_t nnz, size_t* bytes) {
@@ -779,7 +798,7 @@ scg_status sketchycgal_summary(scg_ctx* c, scg_summary* o) {
     o->spmv_lanes = c->lanes;
     o->spmv_segments = c->nseg;
     o->matrix_format = c->fmt;
-    o->pad = 0;
+    o->spmv_grid = c->Gs;
     return (hsc.flags & 2) ? SCG_ENUMERIC : SCG_OK;
 }
 

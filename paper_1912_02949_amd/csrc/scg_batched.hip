@@ -1508,6 +1508,7 @@ scg_status sketchycgal_batch_summary(scg_batch* c, int32_t inst, scg_summary* o)
     o->objective = I.c_F * I.alpha * hs.p / I.alpha_s;
     o->infeasibility = I.alpha / I.alpha_s * infeas;
     o->matrix_format = c->fmt;
+    o->spmv_grid = c->ninst;
     return (hs.flags & 2) ? SCG_ENUMERIC : SCG_OK;
 }
 

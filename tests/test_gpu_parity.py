@@ -68,6 +68,26 @@ def test_apply_matches_operator(which, precision, tol, matrix_format, cfg1):
     assert maxrel(y, ref) < tol
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+@pytest.mark.parametrize("lanes,grid", [(2, 16), (4, 8), (8, 0), (32, 24)])
+def test_apply_with_forced_spmv_shape(lanes, grid, precision, tol):
+    """Fewer workgroups than row-block ranges (each wave walks several blocks)
+    and every lane count give the same product."""
+    need_gpu()
+    inst = synth.laplacian_instance(synth.torus_longrange(256, 77))
+    s = make_solver(inst, R=4, T=5, seed=3, precision=precision, spmv_lanes=lanes, spmv_grid=grid)
+    summ = s.summary()
+    assert summ["spmv_lanes"] == lanes
+    if grid:
+        assert 8 <= summ["spmv_grid"] <= grid
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(inst.n)
+    y = s.apply(x).cpu().numpy()
+    Cs, bs, _, _ = scale_problem(inst.to_scipy(), inst.b, float(inst.n))
+    ref = Cs @ x + math.sqrt(2.0) * (0 - bs) * x
+    assert maxrel(y, ref) < tol
+
+
 def test_first_lanczos_run_matches(cfg1):
     need_gpu()
     s = make_solver(cfg1, R=10, T=3, seed=SEED1, q_mode=1, q_fixed=8)
