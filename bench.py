@@ -9,6 +9,10 @@ reconstruction.  `value` is CGAL iterations per second of the FP32-stream
 form; the plain-FP64 form is timed beside it.
 
 Also reported:
+  fp64_plain    the plain-FP64 solve, and the FP32 solve stopped where its
+                ||diag X - b|| first reaches the FP64 solve's final value
+                (speedup at equal final infeasibility)
+  spmv_other_workloads  the Lanczos SpMV alone on workloads 5 and 3 (roofline context)
   batched       the batched form: 256 Erdos-Renyi instances (average degree 8,
                 n uniform in [200, 20000]), R = 8, T = 1000, all advanced by one
                 launch per iteration; instance-iterations per second, FP32 and FP64
@@ -108,6 +112,16 @@ class Solve:
         self.lib.sketchycgal_summary(self.ctx, C.byref(s))
         return {k: getattr(s, k) for k, _ in _lib.scg_summary._fields_}
 
+    def infeasibility_log(self):
+        """||diag X_{t+1} - b|| per iteration, original units."""
+        from paper_1912_02949_amd import _lib
+        cap = self.prm.T
+        arr = (_lib.scg_iter_log * cap)()
+        cnt = C.c_int32()
+        _lib.check(self.lib.sketchycgal_log(self.ctx, arr, cap, C.byref(cnt)), "log")
+        s = self.summary()
+        return [arr[i].infeas * s["alpha"] / s["alpha_scaled"] for i in range(cnt.value)]
+
 
 def timed(solve: Solve, steps: int, warmup: int, torch):
     for _ in range(warmup):
@@ -157,6 +171,29 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def spmv_line(torch, k: int, precision: str):
+    """Lanczos SpMV of workload k alone: autotuned shape, 50 back-to-back launches (HIP events)."""
+    import synth
+    from paper_1912_02949_amd import Params
+    inst = synth.config_instance(k)
+    sp = Solve(inst, Params(R=10, T=100, seed=synth.CONFIG_SEEDS[k], precision=precision), torch)
+    sp.init()
+    sp.lib.sketchycgal_step(sp.ctx, 2)
+    ms = C.c_double()
+    sp.lib.sketchycgal_time_spmv(sp.ctx, 50, C.byref(ms))
+    summ = sp.summary()
+    sp.close()
+    es = 4 if precision == "fp32" else 8
+    nnz_off = inst.nnz - inst.n
+    per_nz = 4 + (es if summ["matrix_format"] == 0 else 0)
+    by = per_nz * nnz_off + 4 * (inst.n + 1) + 3 * es * inst.n
+    gbs = by / (ms.value * 1e-3) / 1e9
+    return {"n": inst.n, "nnz_offdiag": nnz_off, "avg_launch_us": ms.value * 1e3, "algorithmic_bytes_per_launch": by,
+            "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "lanes_per_row": summ["spmv_lanes"],
+            "column_segments": summ["spmv_segments"], "workgroups": summ["spmv_grid"],
+            "matrix_format": ["values", "columns only", "columns with sign bit"][summ["matrix_format"]]}
+
+
 def batched_leg(torch, T: int, with_fp64: bool):
     """Whole batched solves (init excluded from the rate, reported beside it)."""
     import synth
@@ -196,6 +233,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--batched-T", type=int, default=1000)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only the SpMV kernel, 20 launches in each shape the autotuner chooses from (lanes per "
@@ -245,6 +283,7 @@ def main():
     dt32 = timed(s32, args.steps, args.warmup, torch)
     progress(f"fp32 solves: {1e3 * dt32 / args.steps:.1f} ms each")
     sum32 = s32.summary()
+    infeas32 = s32.infeasibility_log()
     # SpMV kernel leg: back-to-back launches on the solver's stream, HIP events
     ms = C.c_double()
     s32.lib.sketchycgal_time_spmv(s32.ctx, 200, C.byref(ms))
@@ -282,9 +321,28 @@ def main():
             "objective": sum64["objective"],
             "infeasibility": sum64["infeasibility"],
         }
+        # speedup at equal final infeasibility: the FP32 solve stopped at the first iteration whose
+        # ||diag X - b|| is at most the FP64 solve's final value, timed as a whole solve
+        hit = next((i + 1 for i, v in enumerate(infeas32) if v <= sum64["infeasibility"]), None)
+        if hit is not None:
+            s_eq = Solve(inst, Params(R=10, T=hit, seed=synth.CONFIG_SEEDS[2], precision="fp32"), torch)
+            dt_eq = timed(s_eq, 1, 0, torch)
+            s_eq.close()
+            fp64["equal_infeasibility"] = {
+                "fp32_iterations": hit, "fp32_ms": 1e3 * dt_eq, "fp64_iterations": T,
+                "fp64_ms": fp64["ms_per_step"], "speedup_fp32_vs_fp64": fp64["ms_per_step"] / (1e3 * dt_eq)}
+            progress(f"fp32 reaches the fp64 final infeasibility at t = {hit}: {1e3 * dt_eq:.1f} ms")
     del s32
 
     batched = None if args.no_batched else batched_leg(torch, args.batched_T, not args.no_fp64)
+    others = None
+    if not args.no_other_workloads:
+        others = {}
+        for k, name in ((5, "random geometric, n=2^23, weights U[0.5,1.5]"),
+                        (3, "Chung-Lu power law, n=2^22, unit weights")):
+            others[f"workload_{k}"] = {"graph": name,
+                                       **{prec: spmv_line(torch, k, prec) for prec in ("fp32", "fp64")}}
+            progress(f"SpMV line for workload {k} done")
     cpu = None if args.no_cpu else cpu_baseline(inst, T, args.cpu_seconds)
 
     value = args.steps * T / dt32
@@ -324,6 +382,7 @@ def main():
         "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "result_fp32": {"objective": sum32["objective"], "infeasibility": sum32["infeasibility"]},
         "batched": batched,
+        "spmv_other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

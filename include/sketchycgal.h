@@ -160,6 +160,18 @@ scg_status sketchycgal_step(scg_ctx* ctx, int32_t iters);
  * tenfold increases of the shift. */
 scg_status sketchycgal_reconstruct(scg_ctx* ctx, double* U, double* lambda, double* err);
 
+/* MaxCut rounding (Section 7.2, sec:maxcut-rounding) of a reconstruction:
+ * the columns of sgn(U) (sgn 0 taken as +1) are R cut indicators chi_j; their
+ * weights -chi_j^T C chi_j (original units; the total weight of the cut
+ * edges when C = -L/4, the MaxCut data) are returned and the heaviest is kept.
+ *   U        device double[n*R] column-major, as written by sketchycgal_reconstruct
+ *   chi      device int8[n]: the heaviest cut (+1 / -1 per vertex), or NULL
+ *   weights  host double[R]: every cut weight
+ *   best     host int32: index of the heaviest (lowest index on ties)
+ * Evaluated on the matrix as stored (values rounded to FP32 in the FP32-stream
+ * precision when they are stored).  Synchronises. */
+scg_status sketchycgal_round(scg_ctx* ctx, const double* U, int8_t* chi, double* weights, int32_t* best);
+
 /* Copy up to `max` iteration records into host memory (synchronises). */
 scg_status sketchycgal_log(scg_ctx* ctx, scg_iter_log* host_out, int32_t max, int32_t* count);
 
@@ -249,6 +261,10 @@ scg_status sketchycgal_batch_set_state(scg_batch* ctx, int32_t inst, int32_t t_n
                                        const double* y, const double* S, double p, double tau);
 scg_status sketchycgal_batch_reconstruct(scg_batch* ctx, int32_t inst, double* U, double* lambda,
                                          double* err);
+/* MaxCut rounding of problem `inst` from its reconstruction U (device
+ * double[n_i*R]); as sketchycgal_round. */
+scg_status sketchycgal_batch_round(scg_batch* ctx, int32_t inst, const double* U, int8_t* chi,
+                                   double* weights, int32_t* best);
 void sketchycgal_batch_destroy(scg_batch* ctx);
 
 #ifdef __cplusplus

@@ -24,3 +24,4 @@ from .sketchycgal import (  # noqa: F401
     OracleParams, OracleResult, lanczos_q, scale_problem, approx_min_evec, tridiag_min_eigpair,
     dual_step_size, NystromSketch, sketchy_cgal, start_vector, gaussian_test_matrix, maxcut_dual_bound,
 )
+from .rounding import cut_indicators, cut_weight, round_maxcut  # noqa: F401

@@ -43,10 +43,10 @@ EXPORTS = [
     "scg_default_params", "scg_workspace_size", "sketchycgal_init", "sketchycgal_step",
     "sketchycgal_reconstruct", "sketchycgal_log", "sketchycgal_summary", "sketchycgal_get_state",
     "sketchycgal_set_state", "sketchycgal_lanczos_coeffs", "sketchycgal_apply", "sketchycgal_time_spmv",
-    "sketchycgal_destroy", "scg_status_string",
+    "sketchycgal_destroy", "scg_status_string", "sketchycgal_round",
     "scg_batch_workspace_size", "sketchycgal_batch_init", "sketchycgal_batch_step", "sketchycgal_batch_log",
     "sketchycgal_batch_summary", "sketchycgal_batch_get_state", "sketchycgal_batch_set_state", "sketchycgal_batch_reconstruct",
-    "sketchycgal_batch_destroy",
+    "sketchycgal_batch_destroy", "sketchycgal_batch_round",
 ]
 
 _lib = None
@@ -86,6 +86,8 @@ def load() -> C.CDLL:
     lib.sketchycgal_batch_get_state.argtypes = [vp, i32, P(i32), vp, vp, vp, P(C.c_double), P(C.c_double)]
     lib.sketchycgal_batch_set_state.argtypes = [vp, i32, i32, vp, vp, vp, C.c_double, C.c_double]
     lib.sketchycgal_batch_reconstruct.argtypes = [vp, i32, vp, vp, vp]
+    lib.sketchycgal_round.argtypes = [vp, vp, vp, P(C.c_double), P(i32)]
+    lib.sketchycgal_batch_round.argtypes = [vp, i32, vp, vp, P(C.c_double), P(i32)]
     lib.sketchycgal_batch_destroy.argtypes = [vp]
     lib.sketchycgal_batch_destroy.restype = None
     lib.scg_status_string.argtypes = [C.c_int]

@@ -118,6 +118,16 @@ class SketchyCGAL:
         check(self.lib.sketchycgal_reconstruct(self.ctx, _ptr(U), _ptr(lam), _ptr(err)), "sketchycgal_reconstruct")
         return U.view(R, self.n).t(), lam, err
 
+    def round_cut(self, U):
+        """MaxCut rounding of a reconstruction U (n x R): every cut weight, the heaviest's index and indicator."""
+        U = _dev(U.t().contiguous().reshape(-1) if isinstance(U, torch.Tensor) else np.asarray(U).T.reshape(-1),
+                 torch.float64, self.device)
+        chi = torch.empty(self.n, dtype=torch.int8, device=self.device)
+        w = (C.c_double * self.params.R)()
+        best = C.c_int32()
+        check(self.lib.sketchycgal_round(self.ctx, _ptr(U), _ptr(chi), w, C.byref(best)), "sketchycgal_round")
+        return np.array(w[:]), best.value, chi
+
     def log(self) -> dict:
         cap = self.params.T
         arr = (_lib.scg_iter_log * cap)()
@@ -278,6 +288,18 @@ class BatchedSketchyCGAL:
         torch.cuda.current_stream(self.device).synchronize()
         check(self.lib.sketchycgal_batch_set_state(self.ctx, inst, int(t), _ptr(z), _ptr(y), _ptr(S), float(p),
                                                    float(tau)), "sketchycgal_batch_set_state")
+
+    def round_cut(self, inst: int, U):
+        """MaxCut rounding of instance `inst` from its reconstruction U (n_i x R)."""
+        n = int(self.inst_n[inst])
+        U = _dev(U.t().contiguous().reshape(-1) if isinstance(U, torch.Tensor) else np.asarray(U).T.reshape(-1),
+                 torch.float64, self.device)
+        chi = torch.empty(n, dtype=torch.int8, device=self.device)
+        w = (C.c_double * self.params.R)()
+        best = C.c_int32()
+        check(self.lib.sketchycgal_batch_round(self.ctx, inst, _ptr(U), _ptr(chi), w, C.byref(best)),
+              "sketchycgal_batch_round")
+        return np.array(w[:]), best.value, chi
 
     def reconstruct(self, inst: int):
         n = int(self.inst_n[inst])

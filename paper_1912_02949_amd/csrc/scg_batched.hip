@@ -910,6 +910,47 @@ __global__ __launch_bounds__(256) void k_bstate_out(int n, int64_t ld, int R, co
     }
 }
 
+// MaxCut rounding of one instance (Section 7.2, sec:maxcut-rounding): per
+// workgroup partial sums of chi_j^T C_off chi_j (j < R, chi_j = sgn U[:, j],
+// sgn 0 = +1) and of tr(C), in scaled units.
+template <typename T, typename CT, int FMT, int RB>
+__global__ __launch_bounds__(256) void k_bcut_forms(int n, const int32_t* rp, const CT* col, const T* val, double cval,
+                                                    const double* dC, const double* U, int R, double* part) {
+    __shared__ double red[4];
+    double acc[RB + 1];
+#pragma unroll
+    for (int j = 0; j <= RB; ++j) acc[j] = 0.0;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+        double off[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) off[j] = 0.0;
+        for (int e = rp[r]; e < rp[r + 1]; ++e) {
+            const CT cw = col[e];
+            const int c = (FMT == FMT_SGN) ? col_index(cw) : (int)cw;
+            const double v = (FMT == FMT_VAL) ? (double)val[e] : ((FMT == FMT_SGN && col_neg(cw)) ? -cval : cval);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                if (j < R) off[j] += v * ((U[(int64_t)j * n + c] < 0.0) ? -1.0 : 1.0);
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if (j < R) acc[j] += ((U[(int64_t)j * n + r] < 0.0) ? -1.0 : 1.0) * off[j];
+        acc[RB] += dC[r];
+    }
+#pragma unroll
+    for (int j = 0; j <= RB; ++j) {
+        double v = wave_sum(acc[j]);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * (RB + 1) + j] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bcut_indicator(int n, const double* u, int8_t* chi) {
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) chi[r] = (u[r] < 0.0) ? (int8_t)-1 : (int8_t)1;
+}
+
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int q_of(const scg_params& p, int64_t n, int t) {
@@ -1584,6 +1625,60 @@ scg_status sketchycgal_batch_reconstruct(scg_batch* c, int32_t inst, double* U, 
     a.lambda = lambda;
     a.err = err;
     return scg_reconstruct_generic(a);
+}
+
+scg_status sketchycgal_batch_round(scg_batch* c, int32_t inst, const double* U, int8_t* chi, double* weights,
+                                   int32_t* best) {
+    if (!c || !U || !weights || !best || inst < 0 || inst >= c->ninst) return SCG_EINVAL;
+    const BatchInst& I = c->hinst[inst];
+    const int R = c->prm.R;
+    const int RBs = (R <= 8) ? 8 : kRMax;
+    const int G = std::max(1, std::min(1024, (I.n + 255) / 256));
+    const int32_t* rp = c->rp + I.row0;
+    const double* dC = c->dC + I.pos0;
+    double* part = c->recon;
+    const dim3 g(G), b(256);
+#define SCG_BCUT(T, CT, FMT, RB)                                                                               \
+    hipLaunchKernelGGL((k_bcut_forms<T, CT, FMT, RB>), g, b, 0, c->stream, I.n, rp, (const CT*)c->col,          \
+                       (const T*)c->val, I.cval, dC, U, R, part)
+#define SCG_BCUT_RB(T, CT, FMT) \
+    do { if (RBs == 8) SCG_BCUT(T, CT, FMT, 8); else SCG_BCUT(T, CT, FMT, kRMax); } while (0)
+#define SCG_BCUT_FMT(T, CT)                                          \
+    do {                                                             \
+        if (c->fmt == FMT_PAT) SCG_BCUT_RB(T, CT, FMT_PAT);          \
+        else if (c->fmt == FMT_SGN) SCG_BCUT_RB(T, CT, FMT_SGN);     \
+        else SCG_BCUT_RB(T, CT, FMT_VAL);                            \
+    } while (0)
+    if (c->prm.precision == SCG_FP32_STREAM) {
+        if (c->col16) SCG_BCUT_FMT(float, uint16_t); else SCG_BCUT_FMT(float, int32_t);
+    } else {
+        if (c->col16) SCG_BCUT_FMT(double, uint16_t); else SCG_BCUT_FMT(double, int32_t);
+    }
+#undef SCG_BCUT_FMT
+#undef SCG_BCUT_RB
+#undef SCG_BCUT
+    HIP_TRY(hipGetLastError());
+    std::vector<double> h((size_t)G * (RBs + 1));
+    HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tr = 0.0;
+    std::vector<double> q(R, 0.0);
+    for (int gi = 0; gi < G; ++gi) {
+        for (int j = 0; j < R; ++j) q[j] += h[(size_t)gi * (RBs + 1) + j];
+        tr += h[(size_t)gi * (RBs + 1) + RBs];
+    }
+    int bi = 0;
+    for (int j = 0; j < R; ++j) {
+        weights[j] = -I.c_F * (q[j] + tr);
+        if (weights[j] > weights[bi]) bi = j;
+    }
+    *best = bi;
+    if (chi) {
+        hipLaunchKernelGGL(k_bcut_indicator, g, b, 0, c->stream, I.n, U + (int64_t)bi * I.n, chi);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return SCG_OK;
 }
 
 void sketchycgal_batch_destroy(scg_batch* c) {

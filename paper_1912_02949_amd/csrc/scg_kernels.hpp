@@ -149,23 +149,35 @@ __device__ __forceinline__ T column_product(const T* __restrict__ x, int cw, T v
     return (cw < 0) ? -xv : xv;
 }
 
+// Products of the block's entries (gathers of x issued together).
 template <typename T, int FMT>
-__device__ __forceinline__ void stage_block(const T* __restrict__ x, int e0, int e1, int lane,
-                                            const BlockRegs<T, FMT>& B, T* stage) {
+__device__ __forceinline__ void gather_block(const T* __restrict__ x, int e0, int e1, int lane,
+                                             const BlockRegs<T, FMT>& B, T (&pr)[kQW][4]) {
+    const int q0 = e0 >> 2, q1 = (e1 + 3) >> 2;
+#pragma unroll
+    for (int j = 0; j < kQW; ++j) {
+        const int qe = q0 + lane + 64 * j;
+        if (qe < q1) {
+            const int cc[4] = {B.c[j].x, B.c[j].y, B.c[j].z, B.c[j].w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                pr[j][i] = column_product<T, FMT>(x, cc[i], FMT == FMT_VAL ? B.v[FMT == FMT_VAL ? j : 0][i] : (T)0);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_products(int e0, int e1, int lane, const T (&pr)[kQW][4], T* stage) {
     const int q0 = e0 >> 2, q1 = (e1 + 3) >> 2;
 #pragma unroll
     for (int j = 0; j < kQW; ++j) {
         const int qe = q0 + lane + 64 * j;
         if (qe < q1) {
             const int eb = qe << 2;
-            const int cc[4] = {B.c[j].x, B.c[j].y, B.c[j].z, B.c[j].w};
-            T pr[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) pr[i] = column_product<T, FMT>(x, cc[i], FMT == FMT_VAL ? B.v[FMT == FMT_VAL ? j : 0][i] : (T)0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int e = eb + i;
-                if (e >= e0 && e < e1) stage[e - e0] = pr[i];
+                if (e >= e0 && e < e1) stage[e - e0] = pr[j][i];
             }
         }
     }
@@ -279,17 +291,37 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
         int2 dD = dC;
         if (rbk + 2 < bhi) dD = sg.rbd[rbk + 3];
         if (nrows == 1 && e1 - e0 > kNB) {
+            if (has_next && !next_long) fetch_block<T, FMT>(P, dB.y, dC.y, lane, cur);
             T a = 0;
             for (int e = e0 + lane; e < e1; e += 64) a += nz_product<T, FMT>(P, x, e, nt_load(P.col + e));
             const double tot = wave_sum((double)a);
             if (lane == 0) finish_row(r0, tot, (double)x[r0], (double)P.s[r0]);
         } else {
-            // (A) gathers for this block
-            stage_block<T, FMT>(x, e0, e1, lane, cur, stage);
-            for (int i = lane; i < nrows; i += 64) {
-                xrow[i] = x[r0 + i];
-                srow[i] = nt_load(P.s + r0 + i);
-                rbeg[i] = nt_load(P.rp + r0 + i) - e0;
+            // (A) the block's row data, its gathers and the next block's entries are
+            // all in flight before any of them is consumed
+            T xr_r[kRowsCap / 64], sr_r[kRowsCap / 64];
+            int rb_r[kRowsCap / 64];
+#pragma unroll
+            for (int h = 0; h < kRowsCap / 64; ++h) {
+                const int i = lane + 64 * h;
+                if (i < nrows) {
+                    xr_r[h] = x[r0 + i];
+                    sr_r[h] = nt_load(P.s + r0 + i);
+                    rb_r[h] = nt_load(P.rp + r0 + i) - e0;
+                }
+            }
+            T pr[kQW][4];
+            gather_block<T, FMT>(x, e0, e1, lane, cur, pr);
+            if (has_next && !next_long) fetch_block<T, FMT>(P, dB.y, dC.y, lane, cur);
+            store_products<T>(e0, e1, lane, pr, stage);
+#pragma unroll
+            for (int h = 0; h < kRowsCap / 64; ++h) {
+                const int i = lane + 64 * h;
+                if (i < nrows) {
+                    xrow[i] = xr_r[h];
+                    srow[i] = sr_r[h];
+                    rbeg[i] = rb_r[h];
+                }
             }
             if (lane == 0) rbeg[nrows] = e1 - e0;
             wave_sync();
@@ -311,7 +343,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
                 finish_row(r0 + i, (double)rsum[i], (double)xrow[i], (double)srow[i]);
             wave_sync();
         }
-        if (has_next && !next_long) fetch_block<T, FMT>(P, dB.y, dC.y, lane, cur);
         dA = dB;
         dB = dC;
         dC = dD;

@@ -180,9 +180,8 @@ __device__ bool chol_lower(const double* A, double shift, int R, double* Lo) {
     return true;
 }
 
-// Largest eigenvalue of a symmetric R x R matrix by cyclic Jacobi.
-__device__ double sym_lambda_max(const double* A0, int R) {
-    double A[kRMax * kRMax];
+// Largest eigenvalue of a symmetric R x R matrix by cyclic Jacobi (A: R x R work array).
+__device__ double sym_lambda_max(const double* A0, int R, double* A) {
     for (int i = 0; i < R * R; ++i) A[i] = A0[i];
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off = 0.0, tot = 0.0;
@@ -227,12 +226,16 @@ __device__ double spacing(double x, int fp32) {
     return ldexp(1.0, e - 1 - 52);
 }
 
+// The R x R work of these one-thread kernels lives in LDS, not in per-lane
+// private memory (which the runtime would have to back with scratch for
+// every wave the device can hold).
+//
 // sigma, B = Omega^T S + sigma Omega^T Omega, Cholesky with retries.
 __global__ void k_small_sigma(int64_t n, int R, int fp32, double* small, Small L) {
+    __shared__ double A[kRMax * kRMax], B[kRMax * kRMax];
     if (threadIdx.x != 0) return;
-    const double lmax = sym_lambda_max(small + L.G0, R);
+    const double lmax = sym_lambda_max(small + L.G0, R, A);
     double sigma = sqrt((double)n) * spacing(sqrt(fmax(lmax, 0.0)), fp32);
-    double B[kRMax * kRMax];
     bool ok = false;
     for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
         for (int i = 0; i < R * R; ++i) B[i] = small[L.P0 + i] + sigma * small[L.Q0 + i];
@@ -263,11 +266,13 @@ __global__ void k_small_chol(int64_t n, int R, double* small, Small L, int dst, 
 // Writes W = L3^{-T} U_r (sorted by decreasing Sigma), Lambda, err.
 __global__ void k_small_svd(int R, double* small, Small L, double tau, double alpha, int trace_correct,
                             double* lambda, double* err) {
+    __shared__ double A[kRMax * kRMax], Tm[kRMax * kRMax];
+    __shared__ double sv[kRMax], u[kRMax], lam[kRMax];
+    __shared__ int order[kRMax];
     if (threadIdx.x != 0) return;
     const double* L1 = small + L.L1;
     const double* L2 = small + L.L2;
     const double* L3 = small + L.L3;
-    double A[kRMax * kRMax], Tm[kRMax * kRMax];
     // Tm = L2^T L1^T = (L1 L2)^T
     for (int i = 0; i < R; ++i)
         for (int j = 0; j < R; ++j) {
@@ -306,8 +311,6 @@ __global__ void k_small_svd(int R, double* small, Small L, double tau, double al
             }
         if (!rotated) break;
     }
-    double sv[kRMax];
-    int order[kRMax];
     for (int j = 0; j < R; ++j) {
         double s = 0.0;
         for (int k = 0; k < R; ++k) s += A[k * R + j] * A[k * R + j];
@@ -324,7 +327,6 @@ __global__ void k_small_svd(int R, double* small, Small L, double tau, double al
     double* W = small + L.W;
     for (int jj = 0; jj < R; ++jj) {
         const int j = order[jj];
-        double u[kRMax];
         const double s = sv[j];
         for (int k = 0; k < R; ++k) u[k] = (s > 0.0) ? A[k * R + j] / s : (k == jj ? 1.0 : 0.0);
         for (int i = R - 1; i >= 0; --i) {
@@ -335,7 +337,7 @@ __global__ void k_small_svd(int R, double* small, Small L, double tau, double al
         for (int k = 0; k < R; ++k) W[k * R + jj] = u[k];
     }
     const double sigma = small[L.scal + 4];
-    double lam[kRMax], tr = 0.0, cum = 0.0;
+    double tr = 0.0, cum = 0.0;
     for (int jj = 0; jj < R; ++jj) {
         const double s = sv[order[jj]];
         lam[jj] = fmax(0.0, s * s - sigma);

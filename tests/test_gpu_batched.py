@@ -244,3 +244,19 @@ def test_batched_validation_errors():
     assert e.value.status == SCG_EINVAL
     bt.step(3)
     assert bt.summary(2)["t_done"] == 10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_batched_rounding_matches_oracle_on_same_reconstruction(precision, tol):
+    need_gpu()
+    from oracle import round_maxcut, cut_indicators
+    insts = valued_batch() + small_batch()[:2]
+    bt = make_batch(insts, R=8, T=60, seed=SEED4, q_mode=1, q_fixed=12, precision=precision)
+    bt.run()
+    for i in range(len(insts)):
+        U, _, _ = bt.reconstruct(i)
+        w, best, chi = bt.round_cut(i, U)
+        w_ref, best_ref, chi_ref = round_maxcut(U.cpu().numpy(), insts[i].to_scipy())
+        assert np.abs(w - w_ref).max() < tol * np.abs(w_ref).max(), i
+        assert w_ref[best] >= w_ref[best_ref] - tol * abs(w_ref[best_ref]), i
+        assert np.array_equal(chi.cpu().numpy(), cut_indicators(U.cpu().numpy())[:, best]), i

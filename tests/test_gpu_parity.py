@@ -335,3 +335,37 @@ def test_validation_errors_on_device():
     with pytest.raises(SCGError) as e:
         s.step(1)
     assert e.value.status == SCG_ESTATE
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+@pytest.mark.parametrize("which", ["cfg1", "star", "pm1"])
+def test_rounding_matches_oracle_on_same_reconstruction(which, precision, tol, cfg1):
+    """MaxCut rounding (Section 7.2): the same U gives the same R cut weights,
+    the same heaviest cut and bit-identical indicators."""
+    need_gpu()
+    from oracle import round_maxcut, cut_indicators
+    inst = {"cfg1": lambda: cfg1, "star": lambda: _star_plus(5000, 3),
+            "pm1": lambda: synth.laplacian_instance(synth.torus_longrange(64, 5))}[which]()
+    s = make_solver(inst, R=6, T=60, seed=SEED1, q_mode=1, q_fixed=12, precision=precision)
+    s.run()
+    U, lam, err = s.reconstruct()
+    w, best, chi = s.round_cut(U)
+    w_ref, best_ref, chi_ref = round_maxcut(U.cpu().numpy(), inst.to_scipy())
+    assert np.abs(w - w_ref).max() < tol * np.abs(w_ref).max()
+    # integer cut weights can tie: the chosen cut must be a heaviest one, its indicator exact
+    assert w_ref[best] >= w_ref[best_ref] - tol * abs(w_ref[best_ref])
+    assert np.array_equal(chi.cpu().numpy(), cut_indicators(U.cpu().numpy())[:, best])
+
+
+@pytest.mark.parametrize("graph,opt", [(synth.complete_bipartite(3, 4), 12.0), (synth.cycle(8), 8.0),
+                                       (synth.cycle(7), 6.0)])
+def test_gpu_solve_reconstruct_round_finds_the_max_cut(graph, opt):
+    need_gpu()
+    inst = synth.laplacian_instance(graph)
+    s = make_solver(inst, R=4, T=2000, seed=1)
+    s.run()
+    U, _, _ = s.reconstruct()
+    w, best, chi = s.round_cut(U)
+    assert w[best] == pytest.approx(opt, abs=1e-9)
+    x = chi.cpu().numpy().astype(np.float64)
+    assert -(x @ (inst.to_scipy() @ x)) == pytest.approx(opt, abs=1e-9)
