@@ -42,8 +42,30 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # SpMV shapes whose HBM traffic the profile records: (lanes per row, workgroups cap, column segments);
 # workgroups 0 = one row-block range per wave
-PROBE_SHAPES = tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2))
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_traffic_torus_1m_fp32.json")
+PROBE_SHAPES = {
+    2: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2)),
+    5: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)),
+}
+TRAFFIC_FILES = {
+    2: os.path.join(ROOT, "profiles", "spmv_traffic_torus_1m_fp32.json"),
+    5: os.path.join(ROOT, "profiles", "spmv_traffic_geometric_8m_fp32.json"),
+}
+
+
+def measured_traffic(k: int, summ: dict):
+    """HBM bytes per SpMV launch of the shape in `summ`, from the committed counter summary of workload k."""
+    path = TRAFFIC_FILES.get(k)
+    if path is None or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    for sh in tr.get("shapes", []):
+        if (sh["lanes"], sh["workgroups"], sh["segments"]) == (summ["spmv_lanes"], summ["spmv_grid"],
+                                                               summ["spmv_segments"]):
+            return sh["hbm_bytes_per_launch"]
+    return None
 KERNEL_SOURCES = ["scg_kernels.hpp", "scg_device.hpp", "scg_internal.hpp"]
 
 
@@ -100,6 +122,18 @@ class Solve:
                                                self.err.data_ptr()), "reconstruct")
         if not keep:
             self.close()
+
+    def round_cut(self):
+        """MaxCut rounding of the last reconstruction: (heaviest cut weight, its index, seconds)."""
+        from paper_1912_02949_amd._lib import check
+        w = (C.c_double * self.prm.R)()
+        best = C.c_int32()
+        chi = self.torch.empty(self.n, dtype=self.torch.int8, device=self.U.device)
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        check(self.lib.sketchycgal_round(self.ctx, self.U.data_ptr(), chi.data_ptr(), w, C.byref(best)), "round")
+        dt = time.perf_counter() - t0
+        return w[best.value], best.value, dt
 
     def close(self):
         if self.ctx is not None:
@@ -171,6 +205,24 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def gather_reference(torch, n: int, count: int, reps: int = 20):
+    """Reference rate of random 4-byte gathers on this GPU: torch.index_select of `count` uniform random int32
+    indices from an n-entry FP32 vector (the size of the torus workload's x and its off-diagonal count), HIP
+    events.  Every index is uniform here, while half of the torus's are local, so the SpMV can exceed it."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(0x5C6A)
+    x = torch.rand(n, device="cuda:0", dtype=torch.float32, generator=g)
+    idx = torch.randint(0, n, (count,), device="cuda:0", generator=g).to(torch.int32)
+    torch.index_select(x, 0, idx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.index_select(x, 0, idx)
+    e1.record()
+    torch.cuda.synchronize()
+    return count * reps / (e0.elapsed_time(e1) * 1e-3)
+
+
 def spmv_line(torch, k: int, precision: str):
     """Lanczos SpMV of workload k alone: autotuned shape, 50 back-to-back launches (HIP events)."""
     import synth
@@ -189,6 +241,7 @@ def spmv_line(torch, k: int, precision: str):
     by = per_nz * nnz_off + 4 * (inst.n + 1) + 3 * es * inst.n
     gbs = by / (ms.value * 1e-3) / 1e9
     return {"n": inst.n, "nnz_offdiag": nnz_off, "avg_launch_us": ms.value * 1e3, "algorithmic_bytes_per_launch": by,
+            "traffic": measured_traffic(k, summ) if precision == "fp32" else None,
             "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "lanes_per_row": summ["spmv_lanes"],
             "column_segments": summ["spmv_segments"], "workgroups": summ["spmv_grid"],
             "matrix_format": ["values", "columns only", "columns with sign bit"][summ["matrix_format"]]}
@@ -235,6 +288,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--batched-T", type=int, default=1000)
+    ap.add_argument("--no-storage-optimal", action="store_true")
+    ap.add_argument("--probe-workload", type=int, default=2, choices=(2, 5),
+                    help="workload of --traffic-probe")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only the SpMV kernel, 20 launches in each shape the autotuner chooses from (lanes per "
                          "row x workgroups), for rocprofv3 --pmc, plus a 256 MiB device copy whose counters "
@@ -256,11 +312,14 @@ def main():
     p64 = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp64")
 
     if args.traffic_probe:
+        kp = args.probe_workload
+        pinst = inst if kp == 2 else synth.config_instance(kp)
+        pqs = qs if kp == 2 else q_schedule(100, pinst.n)
         shapes = []
-        for lanes, grid, seg in PROBE_SHAPES:
-            prm = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp32", autotune=0, segments=seg,
-                         spmv_lanes=lanes, spmv_grid=grid)
-            sp = Solve(inst, prm, torch)
+        for lanes, grid, seg in PROBE_SHAPES[kp]:
+            prm = Params(R=10, T=100 if kp != 2 else T, seed=synth.CONFIG_SEEDS[kp], precision="fp32", autotune=0,
+                         segments=seg, spmv_lanes=lanes, spmv_grid=grid)
+            sp = Solve(pinst, prm, torch)
             sp.init()
             sp.lib.sketchycgal_step(sp.ctx, 2)
             ms = C.c_double()
@@ -268,14 +327,14 @@ def main():
             summ = sp.summary()
             sp.close()
             shapes.append({"lanes": lanes, "workgroups": summ["spmv_grid"], "segments": summ["spmv_segments"],
-                           "spmv_avg_us": ms.value * 1e3, "lanczos_launches_before_timing": sum(qs[:2])})
+                           "spmv_avg_us": ms.value * 1e3, "lanczos_launches_before_timing": sum(pqs[:2])})
             progress(f"probe lanes={lanes} workgroups={summ['spmv_grid']} segments={seg}: {ms.value * 1e3:.1f} us")
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"shapes": shapes, "copy_bytes": 4 * a.numel(),
+        print(json.dumps({"workload": kp, "shapes": shapes, "copy_bytes": 4 * a.numel(),
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
         return
 
@@ -284,6 +343,7 @@ def main():
     progress(f"fp32 solves: {1e3 * dt32 / args.steps:.1f} ms each")
     sum32 = s32.summary()
     infeas32 = s32.infeasibility_log()
+    cut_w, cut_j, cut_s = s32.round_cut()
     # SpMV kernel leg: back-to-back launches on the solver's stream, HIP events
     ms = C.c_double()
     s32.lib.sketchycgal_time_spmv(s32.ctx, 200, C.byref(ms))
@@ -298,15 +358,8 @@ def main():
     achieved = bytes_per_launch / (spmv_ms * 1e-3) / 1e9
 
     # measured HBM bytes per launch of the shape the autotuner chose (same kernel source only)
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_sha") == kernel_source_sha():
-            for sh in tr.get("shapes", []):
-                if (sh["lanes"], sh["workgroups"], sh["segments"]) == (sum32["spmv_lanes"], sum32["spmv_grid"],
-                                                                       sum32["spmv_segments"]):
-                    traffic = sh["hbm_bytes_per_launch"]
+    traffic = measured_traffic(2, sum32)
+    gref = gather_reference(torch, n, nnz_off)
 
     fp64 = None
     if not args.no_fp64:
@@ -332,7 +385,28 @@ def main():
                 "fp32_iterations": hit, "fp32_ms": 1e3 * dt_eq, "fp64_iterations": T,
                 "fp64_ms": fp64["ms_per_step"], "speedup_fp32_vs_fp64": fp64["ms_per_step"] / (1e3 * dt_eq)}
             progress(f"fp32 reaches the fp64 final infeasibility at t = {hit}: {1e3 * dt_eq:.1f} ms")
+    ws32 = s32.nbytes
     del s32
+
+    # storage-optimal mode: three Lanczos vectors (basis regenerated by a second sweep) and
+    # Omega regenerated from its counters; same arithmetic, so the same iterates
+    storage = None
+    if not args.no_storage_optimal:
+        # the SpMV shape the autotuner picked for the stored-mode solve, so both run the same products
+        pso = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp32", basis_mode=1, omega_mode=1,
+                     autotune=0, segments=sum32["spmv_segments"], spmv_lanes=sum32["spmv_lanes"],
+                     spmv_grid=sum32["spmv_grid"] if sum32["spmv_grid"] <= 2048 else 0)
+        sso = Solve(inst, pso, torch)
+        dtso = timed(sso, 1, 0, torch)
+        sumso = sso.summary()
+        sso.close()
+        storage = {
+            "value": T / dtso, "unit": "CGAL iters/s", "ms_per_step": 1e3 * dtso,
+            "workspace_bytes": sso.nbytes, "workspace_bytes_stored_mode": ws32,
+            "workspace_ratio": sso.nbytes / ws32,
+            "objective_equals_stored_mode": sumso["objective"] == sum32["objective"],
+        }
+        progress(f"storage-optimal fp32 solve: {1e3 * dtso:.1f} ms")
 
     batched = None if args.no_batched else batched_leg(torch, args.batched_T, not args.no_fp64)
     others = None
@@ -374,13 +448,22 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_us": spmv_ms * 1e3,
+            "gathers_per_s": nnz_off / (spmv_ms * 1e-3),
+            "uniform_gather_reference_per_s": gref,
+            "gathers_over_uniform_reference": nnz_off / (spmv_ms * 1e-3) / gref,
+            "uniform_gather_reference_method": "torch.index_select of nnz_offdiag uniform random int32 indices from "
+                                               "an n-entry FP32 vector on the same GPU (the SpMV makes one gather per "
+                                               "off-diagonal entry; half of the torus's are local, none here)",
         },
         "spmv_tuning": {"lanes_per_row": sum32["spmv_lanes"], "column_segments": sum32["spmv_segments"],
                         "workgroups": sum32["spmv_grid"],
                         "matrix_format": ["values", "columns only", "columns with sign bit"][sum32["matrix_format"]]},
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
-        "result_fp32": {"objective": sum32["objective"], "infeasibility": sum32["infeasibility"]},
+        "result_fp32": {"objective": sum32["objective"], "infeasibility": sum32["infeasibility"],
+                        "rounded_cut_weight": cut_w, "rounded_cut_column": cut_j, "rounding_ms": 1e3 * cut_s,
+                        "cut_over_sdp_objective": cut_w / -sum32["objective"]},
+        "storage_optimal_fp32": storage,
         "batched": batched,
         "spmv_other_workloads": others,
         "cpu_baseline": cpu,

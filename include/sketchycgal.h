@@ -79,6 +79,16 @@ typedef struct {
                                row length, or 2, 4, 8, 16, 32                                 */
     int32_t  spmv_grid;     /* SpMV workgroups: 0 = autotuned / one row-block range per wave,
                                or a cap (rounded to a multiple of 8, at most 2048)            */
+    int32_t  basis_mode;    /* Lanczos basis storage: 0 = all q+1 vectors kept (ld x (q+1)),
+                               1 = three rotating vectors; the Ritz vector is rebuilt by a
+                               second Lanczos pass that regenerates the basis bitwise (the
+                               storage-optimal randomized Lanczos of Section 4.2, alg
+                               rand-lanczos; 0 is the time-storage trade-off its remark
+                               describes).  1 requires reorth = 0 (singleton engine only)     */
+    int32_t  omega_mode;    /* test matrix: 0 = stored n x R (from Philox or the caller),
+                               1 = regenerated from the Philox counters wherever it is used
+                               (no n x R array; the caller may not pass omega).  Singleton
+                               engine only                                                    */
 } scg_params;
 
 /* One record per iteration t, in scaled units (see file comment).  Gap and

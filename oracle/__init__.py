@@ -21,7 +21,8 @@ closed-form MaxCut SDP values and brute force.
 """
 from .philox import philox4x64_10, normal_stream, uniform_pair  # noqa: F401
 from .sketchycgal import (  # noqa: F401
-    OracleParams, OracleResult, lanczos_q, scale_problem, approx_min_evec, tridiag_min_eigpair,
+    OracleParams, OracleResult, lanczos_q, scale_problem, approx_min_evec, approx_min_evec_regenerated,
+    tridiag_min_eigpair,
     dual_step_size, NystromSketch, sketchy_cgal, start_vector, gaussian_test_matrix, maxcut_dual_bound,
 )
 from .rounding import cut_indicators, cut_weight, round_maxcut  # noqa: F401

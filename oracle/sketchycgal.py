@@ -19,7 +19,8 @@ Readings of points the paper leaves open (the library takes the same ones):
       uses omega_1..k and rho_1..k-1.  An exact zero test never fires.
   R4  The Ritz vector is renormalised to unit length.
   R5  The Lanczos basis is stored (Remark "time-storage tradeoff"); in exact
-      arithmetic this equals regenerating it.
+      arithmetic this equals regenerating it, which approx_min_evec_regenerated
+      does (the storage-optimal form of Section 4.2).
   R6  gamma = beta0 when ||z - b|| = 0; ||A|| = 1 for A = diag.
   R7  Scaling: C <- C / ||C||_F, b <- b / alpha, alpha <- 1 (||A|| = 1 and
       ||A_i||_F = 1 already hold for A = diag).  Reported objective and
@@ -168,6 +169,50 @@ def approx_min_evec(matvec, g: np.ndarray, q: int, reorth: int = 0):
     x = np.zeros_like(g)
     for j in range(k):
         x = x + uu[j] * basis[j]
+    x = x / np.linalg.norm(x)
+    return xi, x, {"k": k, "broke": broke, "omega": np.array(omega), "rho": np.array(rho[: k - 1])}
+
+
+def approx_min_evec_regenerated(matvec, g: np.ndarray, q: int):
+    """Storage-optimal randomized Lanczos (alg:rand-lanczos as Section 4.2 states it).
+
+    Only the two most recent Lanczos vectors are ever held.  The first sweep
+    records the tridiagonal coefficients; the minimum eigenvector u of T_k is
+    computed; the second sweep restarts the same recurrence from the same
+    start vector and sums u_j v_j as the vectors come back.  Returns what
+    approx_min_evec returns (reading R5: in exact arithmetic the two agree).
+    """
+    def sweep(coef):
+        v = g / np.linalg.norm(g)
+        v_prev = np.zeros_like(v)
+        rho_prev = 0.0
+        omega, rho = [], []
+        x = np.zeros_like(g)
+        broke = False
+        for i in range(1, q + 1):
+            if coef is not None:
+                if i > len(coef):
+                    break
+                x = x + coef[i - 1] * v
+            u = matvec(v)
+            om = float(np.dot(v, u))
+            u = u - om * v - rho_prev * v_prev
+            r = float(np.linalg.norm(u))
+            omega.append(om)
+            if r <= 64.0 * EPS64 * (abs(om) + rho_prev):
+                broke = True
+                break
+            if i == q:
+                break
+            rho.append(r)
+            v_prev, v = v, u / r
+            rho_prev = r
+        return omega, rho, broke, x
+
+    omega, rho, broke, _ = sweep(None)
+    k = len(omega)
+    xi, uu = tridiag_min_eigpair(np.array(omega), np.array(rho[: k - 1]))
+    _, _, _, x = sweep(uu)
     x = x / np.linalg.norm(x)
     return xi, x, {"k": k, "broke": broke, "omega": np.array(omega), "rho": np.array(rho[: k - 1])}
 

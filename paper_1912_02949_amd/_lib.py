@@ -18,6 +18,7 @@ class scg_params(C.Structure):
         ("scale", C.c_int32), ("trace_correct", C.c_int32), ("reorth", C.c_int32),
         ("precision", C.c_int32), ("instance", C.c_int32), ("matrix_format", C.c_int32),
         ("autotune", C.c_int32), ("segments", C.c_int32), ("spmv_lanes", C.c_int32), ("spmv_grid", C.c_int32),
+        ("basis_mode", C.c_int32), ("omega_mode", C.c_int32),
     ]
 
 

@@ -37,6 +37,8 @@ class Params:
     segments: int = 0             # SpMV column segments: 0 auto, or 1, 2, 4
     spmv_lanes: int = 0           # SpMV lanes per row: 0 auto, or 2, 4, 8, 16, 32
     spmv_grid: int = 0            # SpMV workgroups: 0 auto, or a cap
+    basis_mode: int = 0           # 0: keep the Lanczos basis; 1: three vectors, basis regenerated
+    omega_mode: int = 0           # 0: store the test matrix; 1: regenerate it from its counters
 
     def to_c(self) -> _lib.scg_params:
         p = _lib.scg_params()
@@ -45,6 +47,7 @@ class Params:
         p.trace_correct, p.reorth, p.instance = self.trace_correct, self.reorth, self.instance
         p.matrix_format, p.autotune, p.segments = self.matrix_format, self.autotune, self.segments
         p.spmv_lanes, p.spmv_grid = self.spmv_lanes, self.spmv_grid
+        p.basis_mode, p.omega_mode = self.basis_mode, self.omega_mode
         p.precision = {"fp64": _lib.SCG_FP64, "fp32": _lib.SCG_FP32_STREAM}[self.precision]
         return p
 

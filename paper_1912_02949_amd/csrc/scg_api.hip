@@ -44,7 +44,7 @@ int qmax_for(const scg_params& p, int64_t n) {
 size_t elem_size(const scg_params& p) { return p.precision == SCG_FP32_STREAM ? 4 : 8; }
 
 struct Layout {
-    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, total;
+    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, racc, total;
     size_t recon_bytes;
 };
 
@@ -64,10 +64,11 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.z = take(8 * n);
     L.y = take(8 * n);
     L.s = take(es * n);
-    L.V = take(es * ld * (size_t)(qm + 1));
+    // the Lanczos basis: all q_t + 1 vectors, or three rotating ones when it is regenerated
+    L.V = take(es * ld * (size_t)(p.basis_mode == 1 ? 3 : qm + 1));
     L.u = take(es * n);
     L.v = take(es * n);
-    L.Om = take(es * ld * R);
+    L.Om = take(p.omega_mode == 1 ? 0 : es * ld * R);   // generated from Philox where used
     L.S = take(es * ld * R);
     L.rb = take(sizeof(int2) * (size_t)kSegMax * (n + 2));
     L.sc = take(sizeof(DevScalars));
@@ -77,6 +78,7 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.logs = take(sizeof(scg_iter_log) * (size_t)p.T);
     L.recon_bytes = 8 * scg_recon_scratch_doubles(n, p.R);
     L.recon = take(L.recon_bytes);
+    L.racc = take(p.basis_mode == 1 ? 8 * ld : 0);
     L.total = off;
     return L;
 }
@@ -101,7 +103,11 @@ Prob<T> prob(scg_ctx* c) {
     P.V = (T*)c->V;
     P.u = (T*)c->u;
     P.v = (T*)c->v;
-    P.Om = (const T*)c->Om;
+    P.Om = (c->prm.omega_mode == 1) ? nullptr : (const T*)c->Om;
+    P.seed = c->prm.seed;
+    P.instance = (uint64_t)c->prm.instance;
+    P.vmod = (c->prm.basis_mode == 1) ? 3 : 0;
+    P.racc = c->racc;
     P.S = (T*)c->S;
     P.rb = c->rb;
     P.nrb = c->nrb;
@@ -145,21 +151,28 @@ void launch_spmv(scg_ctx* c, const T* x, int step, int lanes = 0) {
     else launch_spmv_f<T, MODE, 8, FMT_VAL>(c, x, step, lanes);
 }
 
+template <typename T, int RB>
+void launch_ritz_rb(scg_ctx* c, const Prob<T>& P, int q) {
+    const dim3 g(c->G), b(kBlock), one(1);
+    if (c->prm.basis_mode == 1) hipLaunchKernelGGL((k_ritz_regen<T, RB>), g, b, 0, c->stream, P, q);
+    else hipLaunchKernelGGL((k_ritz<T, RB>), g, b, 0, c->stream, P);
+    hipLaunchKernelGGL((k_ritz_fin<RB>), one, b, 0, c->stream, c->sc, P.p_ritz, c->G, c->prm.R);
+}
+
 template <typename T>
-void launch_ritz(scg_ctx* c) {
+void launch_ritz(scg_ctx* c, int q) {
     Prob<T> P = prob<T>(c);
-    dim3 g(c->G), b(kBlock), one(1);
     const int R = c->prm.R;
-    if (R <= 8) {
-        hipLaunchKernelGGL((k_ritz<T, 8>), g, b, 0, c->stream, P);
-        hipLaunchKernelGGL((k_ritz_fin<8>), one, b, 0, c->stream, c->sc, P.p_ritz, c->G, R);
-    } else if (R <= 16) {
-        hipLaunchKernelGGL((k_ritz<T, 16>), g, b, 0, c->stream, P);
-        hipLaunchKernelGGL((k_ritz_fin<16>), one, b, 0, c->stream, c->sc, P.p_ritz, c->G, R);
-    } else {
-        hipLaunchKernelGGL((k_ritz<T, 32>), g, b, 0, c->stream, P);
-        hipLaunchKernelGGL((k_ritz_fin<32>), one, b, 0, c->stream, c->sc, P.p_ritz, c->G, R);
-    }
+    if (R <= 8) launch_ritz_rb<T, 8>(c, P, q);
+    else if (R <= 16) launch_ritz_rb<T, 16>(c, P, q);
+    else launch_ritz_rb<T, 32>(c, P, q);
+}
+
+// Column i of the Lanczos basis (three rotating columns when it is regenerated).
+template <typename T>
+const T* basis_col(scg_ctx* c, int i) {
+    const int j = (c->prm.basis_mode == 1) ? i % 3 : i;
+    return (const T*)c->V + (size_t)j * c->ld;
 }
 
 template <typename T>
@@ -194,22 +207,30 @@ template <typename T>
 void enqueue_iteration(scg_ctx* c, int t) {
     const IterArgs it = iter_args(c, t);
     Prob<T> P = prob<T>(c);
-    const T* V = (const T*)c->V;
     enqueue_prep<T>(c, it);
     for (int i = 0; i < it.q; ++i) {
-        launch_spmv<T, SPMV_LANCZOS>(c, V + (size_t)i * c->ld, i);
+        launch_spmv<T, SPMV_LANCZOS>(c, basis_col<T>(c, i), i);
         if (i == it.q - 1) break;   // rho_q and v_{q+1} are never used
         if (c->prm.reorth == 2) {
-            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 0);
+            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 0, 0);
             hipLaunchKernelGGL((k_reorth_dot<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i);
             hipLaunchKernelGGL(k_reduce_h, dim3(1), dim3(kBlock), 0, c->stream, c->sc, P.p_h, c->G, i);
             hipLaunchKernelGGL((k_reorth_apply<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i);
         } else {
-            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 1);
+            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 1, 0);
         }
     }
     hipLaunchKernelGGL((k_tridiag<T>), dim3(1), dim3(kBlock), 0, c->stream, P, it.q);
-    launch_ritz<T>(c);
+    if (c->prm.basis_mode == 1) {
+        // second pass: the same recurrence regenerates v_0 .. v_{k-1} (bitwise, the
+        // products are deterministic) and k_lupdate accumulates the Ritz vector
+        enqueue_prep<T>(c, it);
+        for (int i = 0; i + 1 < it.q; ++i) {
+            launch_spmv<T, SPMV_LANCZOS>(c, basis_col<T>(c, i), i);
+            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 1, 1);
+        }
+    }
+    launch_ritz<T>(c, it.q);
     launch_spmv<T, SPMV_OBJ>(c, (const T*)c->v, 0);
     hipLaunchKernelGGL((k_primal<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, it);
     launch_dual_sketch<T>(c, it);
@@ -617,7 +638,9 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     hipLaunchKernelGGL((k_scatter<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, c->rp,
                        c->col, (T*)c->val, dCraw, c->dC, c->b, inv_cF, inv_alpha, c->fmt);
     HIP_TRY(hipGetLastError());
-    if (omega) {
+    if (c->prm.omega_mode == 1) {
+        // Omega is generated from Philox wherever it is used
+    } else if (omega) {
         transpose_cast<double, T>(c, omega, (T*)c->Om, 1);
     } else {
         const int64_t total = (n + 3) / 4 * c->prm.R;
@@ -662,6 +685,9 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     const int l = p->spmv_lanes;
     if (l != 0 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
     if (p->spmv_grid < 0 || p->spmv_grid > kGMax) return false;
+    if (p->basis_mode != 0 && p->basis_mode != 1) return false;
+    if (p->basis_mode == 1 && p->reorth != 0) return false;   // reorthogonalisation needs the stored basis
+    if (p->omega_mode != 0 && p->omega_mode != 1) return false;
     return true;
 }
 
@@ -690,6 +716,8 @@ void scg_default_params(scg_params* p) {
     p->segments = 0;
     p->spmv_lanes = 0;
     p->spmv_grid = 0;
+    p->basis_mode = 0;
+    p->omega_mode = 0;
 }
 
 scg_status scg_workspace_size(const scg_params* p, int64_t n, int64_t nnz, size_t* bytes) {
@@ -706,6 +734,7 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     if (!params_ok(p, n, nnz) || !row_ptr || !b || !workspace) return SCG_EINVAL;
     if (nnz > 0 && (!col || !val)) return SCG_EINVAL;
     if (((uintptr_t)workspace & 255) != 0) return SCG_EINVAL;
+    if (omega && p->omega_mode == 1) return SCG_EINVAL;   // a generated Omega is the Philox one
     const Layout L = make_layout(*p, n, nnz);
     if (ws_bytes < L.total) return SCG_ENOMEM;
     scg_ctx* c = new (std::nothrow) scg_ctx();
@@ -731,6 +760,7 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->u = base + L.u;
     c->v = base + L.v;
     c->Om = base + L.Om;
+    c->racc = (p->basis_mode == 1) ? (double*)(base + L.racc) : nullptr;
     c->S = base + L.S;
     c->rb = (int32_t*)(base + L.rb);
     c->rb_cap = (size_t)kSegMax * (n + 2);

@@ -1373,6 +1373,7 @@ bool bparams_ok(const scg_params* p, int ninst, const int64_t* inst_n) {
     if (p->reorth != 0 && p->reorth != 2) return false;
     if (p->precision != SCG_FP64 && p->precision != SCG_FP32_STREAM) return false;
     if (p->matrix_format != 0 && p->matrix_format != 1) return false;
+    if (p->basis_mode != 0 || p->omega_mode != 0) return false;   // the batch keeps both in HBM
     int64_t total = 0;
     for (int k = 0; k < ninst; ++k) {
         const int64_t n = inst_n[k];
@@ -1615,6 +1616,8 @@ scg_status sketchycgal_batch_reconstruct(scg_batch* c, int32_t inst, double* U, 
     a.fp32 = (c->prm.precision == SCG_FP32_STREAM);
     a.S = (const char*)c->S + es * I.off_OS;
     a.Om = (const char*)c->Om + es * I.off_OS;
+    a.seed = c->prm.seed;
+    a.instance = (uint64_t)I.id;
     a.tau = hs.tau;
     a.alpha = I.alpha_s;
     a.trace_correct = c->prm.trace_correct;

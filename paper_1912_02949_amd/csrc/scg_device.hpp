@@ -233,4 +233,22 @@ __device__ __forceinline__ void normal4(uint64_t seed, uint64_t blk, uint64_t in
     }
 }
 
+// Quad 4 qd .. 4 qd + 3 of column c of the Gaussian test matrix Omega, drawn
+// from Philox (seed; quad, column, instance, purpose 1) exactly as it is when
+// stored, rounded to the storage type T; zeros past the m rows that exist.
+template <typename T>
+__device__ __forceinline__ void omega_quad(uint64_t seed, uint64_t instance, int64_t qd, int c, int m,
+                                           double (&o)[4]) {
+    double g[4];
+    normal4(seed, (uint64_t)qd, (uint64_t)c, instance, 1ull, g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = (j < m) ? (double)(T)g[j] : 0.0;
+}
+template <typename T>
+__device__ __forceinline__ double omega_entry(uint64_t seed, uint64_t instance, int64_t r, int c) {
+    double g[4];
+    normal4(seed, (uint64_t)(r >> 2), (uint64_t)c, instance, 1ull, g);
+    return (double)(T)g[r & 3];
+}
+
 }  // namespace scg

@@ -39,7 +39,7 @@ struct DevScalars {
     double c_F, alpha_s;
     int32_t k, done, flags, t_done;
     int32_t err;                               // init validation bits
-    int32_t pad;
+    int32_t kr;                                // Lanczos steps of the current Ritz vector
 };
 
 // Problem description passed by value to kernels.
@@ -57,10 +57,13 @@ struct Prob {
     double* y;
     T* s;                 // diagonal shift of D: dC + y + beta (z - b)
     int64_t ld;           // column stride of V, Omega, S: n rounded up to 64
-    T* V;                 // Lanczos basis, (qmax+1) columns of stride ld
+    T* V;                 // Lanczos basis, (qmax+1) columns of stride ld, or 3 rotating columns (vmod = 3)
+    int vmod;             // 0: column i at i*ld; 3: column i at (i mod 3)*ld (basis regenerated)
+    double* racc;         // Ritz vector accumulator, FP64 (basis regenerated), else null
     T* u;                 // SpMV output
     T* v;                 // Ritz vector (unnormalised)
-    const T* Om;          // Omega, n x R column-major (column c at c*ld)
+    const T* Om;          // Omega, n x R column-major (column c at c*ld), or null: generated from Philox
+    uint64_t seed, instance;   // Philox key and counter word of Omega (and the start vectors)
     T* S;                 // sketch, n x R column-major (column c at c*ld)
     const int32_t* rb;    // row-block boundaries, int32[nrb+1]
     int nrb;
@@ -78,6 +81,11 @@ struct Prob {
     scg_iter_log* logs;
     int T_iters;
 };
+
+template <typename T>
+__device__ __forceinline__ T* vcol(const Prob<T>& P, int i) {
+    return P.V + (size_t)(P.vmod ? i % P.vmod : i) * P.ld;
+}
 
 }  // namespace scg
 
@@ -124,6 +132,7 @@ struct scg_ctx {
     unsigned* counter;  // last-workgroup ticket (initialisation and reconstruction)
     scg_iter_log* logs;
     double* recon;   // reconstruction scratch (n x R FP64 and small matrices)
+    double* racc;    // FP64 Ritz accumulator (regenerated basis), else null
     size_t recon_bytes;
 };
 
@@ -133,7 +142,8 @@ struct ReconArgs {
     int64_t n, ld;
     int R, fp32, trace_correct;
     const void* S;
-    const void* Om;
+    const void* Om;       // or null: Omega generated from Philox (seed, instance)
+    uint64_t seed, instance;
     double tau, alpha;
     double* scratch;      // scg_recon_scratch_doubles(n, R) doubles
     unsigned* counter;    // zeroed ticket word

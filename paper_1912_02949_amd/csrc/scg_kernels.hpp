@@ -10,6 +10,9 @@
 //           [k_reorth_dot, k_reduce_h, k_reorth_apply: full reorthogonalisation] }
 //   k_tridiag     (xi, u) = MinEvec(T_k) in FP64, Ritz coefficients
 //   k_ritz        v = sum_j u_j v_j, ||v||, v^T Omega
+//                 (regenerated basis: k_prep and q_t - 1 x {k_spmv, k_lupdate} run
+//                 again, identically, with k_lupdate adding u_j v_j into an FP64
+//                 accumulator, and k_ritz_regen adds the last term)
 //   k_spmv<OBJ>   v^T C v (objective tracker), ||D v - xi v||
 //   k_primal      z <- (1-eta) z + eta alpha v.v (primitive 3), ||z - b||
 //   k_dual_sketch dual step size, y <- y + gamma (z - b),
@@ -43,23 +46,25 @@ struct IterArgs {
     uint64_t instance;
 };
 
-// Streaming (read-once) data is loaded nontemporally so it does not evict
-// the gathered x entries from L2.
+// Matrix entries move as 16-byte vectors.  They are loaded with the default
+// cache policy: a nontemporal hint on this stream measured 13% slower on the
+// torus workload (random gathers from a 4 MiB vector) and no faster on the
+// geometric one.
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
 typedef int i32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void load_vals4(const float* p, float (&v)[4]) {
-    const f32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(p));
+    const f32x4_t t = *reinterpret_cast<const f32x4_t*>(p);
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 __device__ __forceinline__ void load_vals4(const double* p, double (&v)[4]) {
-    const f64x2_t a = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(p));
-    const f64x2_t b = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(p) + 1);
+    const f64x2_t a = reinterpret_cast<const f64x2_t*>(p)[0];
+    const f64x2_t b = reinterpret_cast<const f64x2_t*>(p)[1];
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 __device__ __forceinline__ int4 load_cols4(const int* p) {
-    const i32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(p));
+    const i32x4_t t = *reinterpret_cast<const i32x4_t*>(p);
     return make_int4(t.x, t.y, t.z, t.w);
 }
 
@@ -94,13 +99,13 @@ __device__ __forceinline__ bool lanczos_breakdown(double rho, double om, double 
 // ranges; the XCD-aware renumbering keeps each XCD on a contiguous eighth
 // of the rows.
 template <typename T>
-__device__ __forceinline__ T nt_load(const T* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ T stream_load(const T* p) { return *p; }
 
 // Product of nonzero e (column word cw) with x, by storage format; the
 // common value of FMT_PAT / FMT_SGN is applied once per row instead.
 template <typename T, int FMT>
 __device__ __forceinline__ T nz_product(const Prob<T>& P, const T* __restrict__ x, int e, int cw) {
-    if (FMT == FMT_VAL) return nt_load(P.val + e) * x[cw];
+    if (FMT == FMT_VAL) return stream_load(P.val + e) * x[cw];
     if (FMT == FMT_PAT) return x[cw];
     const T xv = x[cw & 0x7fffffff];
     return (cw < 0) ? -xv : xv;
@@ -132,8 +137,8 @@ __device__ __forceinline__ void fetch_block(const Prob<T>& P, int e0, int e1, in
                 for (int i = 0; i < 4; ++i) {
                     const int e = eb + i;
                     const bool ok = (e >= e0 && e < e1);
-                    cc[i] = ok ? nt_load(P.col + e) : 0;
-                    if (FMT == FMT_VAL) B.v[FMT == FMT_VAL ? j : 0][i] = ok ? nt_load(P.val + e) : (T)0;
+                    cc[i] = ok ? stream_load(P.col + e) : 0;
+                    if (FMT == FMT_VAL) B.v[FMT == FMT_VAL ? j : 0][i] = ok ? stream_load(P.val + e) : (T)0;
                 }
                 B.c[j] = make_int4(cc[0], cc[1], cc[2], cc[3]);
             }
@@ -293,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
         if (nrows == 1 && e1 - e0 > kNB) {
             if (has_next && !next_long) fetch_block<T, FMT>(P, dB.y, dC.y, lane, cur);
             T a = 0;
-            for (int e = e0 + lane; e < e1; e += 64) a += nz_product<T, FMT>(P, x, e, nt_load(P.col + e));
+            for (int e = e0 + lane; e < e1; e += 64) a += nz_product<T, FMT>(P, x, e, stream_load(P.col + e));
             const double tot = wave_sum((double)a);
             if (lane == 0) finish_row(r0, tot, (double)x[r0], (double)P.s[r0]);
         } else {
@@ -306,8 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
                 const int i = lane + 64 * h;
                 if (i < nrows) {
                     xr_r[h] = x[r0 + i];
-                    sr_r[h] = nt_load(P.s + r0 + i);
-                    rb_r[h] = nt_load(P.rp + r0 + i) - e0;
+                    sr_r[h] = stream_load(P.s + r0 + i);
+                    rb_r[h] = stream_load(P.rp + r0 + i) - e0;
                 }
             }
             T pr[kQW][4];
@@ -380,25 +385,33 @@ __device__ __forceinline__ int quad_rows(int64_t r, int64_t n) { return (int)((n
 
 // omega_step from the SpMV partials; w = u - omega v_step - rho v_{step-1}
 // stored as V[step+1]; partial sums of ||w||^2 (unless reorthogonalising).
+// With accum (the second pass of a regenerated basis) it also adds
+// coef_step * V[step] into the FP64 Ritz accumulator, in the order and with
+// the rounding k_ritz uses.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lupdate(Prob<T> P, int step, int with_norm) {
+__global__ __launch_bounds__(kBlock) void k_lupdate(Prob<T> P, int step, int with_norm, int accum) {
     DevScalars* sc = P.sc;
     if (sc->done) return;
     const int64_t n = P.n;
-    const T* vi = P.V + (size_t)step * P.ld;
-    const T* vm = (step > 0) ? P.V + (size_t)(step - 1) * P.ld : vi;
-    T* out = P.V + (size_t)(step + 1) * P.ld;
+    const T* vi = vcol(P, step);
+    const T* vm = (step > 0) ? vcol(P, step - 1) : vi;
+    T* out = vcol(P, step + 1);
     int64_t qlo, qhi;
     split_range((n + 3) / 4, xcd_lid(), gridDim.x, qlo, qhi);
     int64_t qd = qlo + threadIdx.x;
-    double u4[4], i4[4], m4[4];
+    double u4[4], i4[4], m4[4], a4[4];
     if (qd < qhi) {   // first quad in flight before the omega reduction
         const int64_t r = 4 * qd;
         const int m = quad_rows(r, n);
         ld4(P.u + r, m, u4);
         ld4(vi + r, m, i4);
         ld4(vm + r, m, m4);
+        if (accum) {
+            if (step > 0) ld4(P.racc + r, m, a4);
+            else a4[0] = a4[1] = a4[2] = a4[3] = 0.0;
+        }
     }
+    const double cj = accum ? sc->coef[step] : 0.0;
     double tot[kWSpmv];
     reduce_partials<kWSpmv>(P.p_spmv, P.Gs, tot);
     const double om = tot[0];
@@ -421,6 +434,11 @@ __global__ __launch_bounds__(kBlock) void k_lupdate(Prob<T> P, int step, int wit
         st4(out + r, m, w);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc += w[j] * w[j];
+        if (accum) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a4[j] += cj * i4[j];
+            st4(P.racc + r, m, a4);
+        }
         qd += kBlock;
         if (qd < qhi) {
             const int64_t r2 = 4 * qd;
@@ -428,6 +446,10 @@ __global__ __launch_bounds__(kBlock) void k_lupdate(Prob<T> P, int step, int wit
             ld4(P.u + r2, m2, u4);
             ld4(vi + r2, m2, i4);
             ld4(vm + r2, m2, m4);
+            if (accum) {
+                if (step > 0) ld4(P.racc + r2, m2, a4);
+                else a4[0] = a4[1] = a4[2] = a4[3] = 0.0;
+            }
         }
     }
     if (with_norm) {
@@ -527,6 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_tridiag(Prob<T> P, int q) {
     __syncthreads();
     for (int i = threadIdx.x; i < k; i += kBlock) sc->coef[i] = x[i] * sc->inv[i];
     if (threadIdx.x == 0) {
+        sc->kr = k;
         sc->xi = xi;
         if (!isfinite(xi)) sc->flags |= 2;
     }
@@ -566,7 +589,54 @@ __global__ __launch_bounds__(kBlock) void k_ritz(Prob<T> P) {
         for (int c = 0; c < RB; ++c)
             if (c < R) {
                 double o[4];
-                ld4(P.Om + (size_t)c * P.ld + r, m, o);
+                if (P.Om) ld4(P.Om + (size_t)c * P.ld + r, m, o);
+                else omega_quad<T>(P.seed, P.instance, qd, c, m, o);
+                acc[c + 1] += a[0] * o[0] + a[1] * o[1] + a[2] * o[2] + a[3] * o[3];
+            }
+    }
+    write_partials<RB + 1>(acc, P.p_ritz);
+}
+
+// Regenerated basis: the second pass ran k_lupdate for steps 0 .. min(k, q-1)-1
+// (a breakdown stops it after step k-1; without one the loop ends at q-2), so
+// racc holds that many terms and the last one, coef_{k-1} V[k-1], is added here
+// when k = q.  Stored, norm and v^T Omega as k_ritz; restores k.
+template <typename T, int RB>
+__global__ __launch_bounds__(kBlock) void k_ritz_regen(Prob<T> P, int q) {
+    DevScalars* sc = P.sc;
+    const int k = sc->kr;
+    const int na = (k < q - 1) ? k : q - 1;
+    const bool add_last = na < k;
+    const double cl = sc->coef[k - 1];
+    const T* Vl = vcol(P, k - 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->k = k;
+    const int64_t n = P.n;
+    const int R = P.R;
+    double acc[RB + 1];
+#pragma unroll
+    for (int c = 0; c <= RB; ++c) acc[c] = 0.0;
+    SCG_FOR_QUADS(n) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        double a[4] = {0, 0, 0, 0};
+        if (na > 0) ld4(P.racc + r, m, a);
+        if (add_last) {
+            double t[4];
+            ld4(Vl + r, m, t);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] += cl * t[i];
+        }
+        st4(P.v + r, m, a);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = (double)(T)a[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[0] += a[i] * a[i];
+#pragma unroll
+        for (int c = 0; c < RB; ++c)
+            if (c < R) {
+                double o[4];
+                if (P.Om) ld4(P.Om + (size_t)c * P.ld + r, m, o);
+                else omega_quad<T>(P.seed, P.instance, qd, c, m, o);
                 acc[c + 1] += a[0] * o[0] + a[1] * o[1] + a[2] * o[2] + a[3] * o[3];
             }
     }

@@ -75,8 +75,9 @@ __device__ void grid_sum_dyn(const double* lds_vals, int W, double* part, unsign
 
 // Pass 0: S^T S, Omega^T S, Omega^T Omega.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int64_t ld, int R, const T* S, const T* Om, double* part,
-                                                  unsigned* counter, double* small, Small L) {
+__global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int64_t ld, int R, const T* S, const T* Om, uint64_t seed,
+                                                  uint64_t inst, double* part, unsigned* counter, double* small,
+                                                  Small L) {
     __shared__ double ts[kTile * kRMax], to[kTile * kRMax];
     __shared__ double acc_l[3 * kRMax * kRMax];
     const int r2 = R * R;
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int64_t ld, int R, 
         for (int e = threadIdx.x; e < rows * R; e += kBlock) {
             const int c = e / rows, rr = e % rows;   // column-major source
             ts[rr * R + c] = (double)S[(int64_t)c * ld + t0 + rr];
-            to[rr * R + c] = (double)Om[(int64_t)c * ld + t0 + rr];
+            to[rr * R + c] = Om ? (double)Om[(int64_t)c * ld + t0 + rr] : omega_entry<T>(seed, inst, t0 + rr, c);
         }
         __syncthreads();
         int a = 0;
@@ -113,9 +114,9 @@ __global__ __launch_bounds__(kBlock) void k_gram0(int64_t n, int64_t ld, int R, 
 // Pass B (sigma = 0, S = A in place): A_r = solve(Lk, A_r)
 // Both accumulate the Gram A^T A of the result.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_trsm_gram(int64_t n, int64_t ld, int R, const T* S, const T* Om, double* A,
-                                                      int first, double* small, Small L, int lsel, double* part,
-                                                      unsigned* counter) {
+__global__ __launch_bounds__(kBlock) void k_trsm_gram(int64_t n, int64_t ld, int R, const T* S, const T* Om, uint64_t seed,
+                                                      uint64_t inst, double* A, int first, double* small, Small L,
+                                                      int lsel, double* part, unsigned* counter) {
     __shared__ double tile[kTile * kRMax];
     __shared__ double Lm[kRMax * kRMax];
     __shared__ double acc_l[kRMax * kRMax];
@@ -133,7 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_trsm_gram(int64_t n, int64_t ld, int
             const int64_t r = t0 + threadIdx.x;
             double x[kRMax];
             for (int c = 0; c < R; ++c)
-                x[c] = first ? ((double)S[(int64_t)c * ld + r] + sigma * (double)Om[(int64_t)c * ld + r])
+                x[c] = first ? ((double)S[(int64_t)c * ld + r] +
+                                sigma * (Om ? (double)Om[(int64_t)c * ld + r] : omega_entry<T>(seed, inst, r, c)))
                              : A[r * R + c];
             // forward substitution with the lower factor: Lm x_new = x
             for (int i = 0; i < R; ++i) {
@@ -378,13 +380,13 @@ scg_status recon_generic(const ReconArgs& a) {
     const T* Om = (const T*)a.Om;
     const dim3 g(kGR), b(kBlock);
     hipStream_t st = a.stream;
-    hipLaunchKernelGGL((k_gram0<T>), g, b, 0, st, n, a.ld, R, S, Om, part, a.counter, small, L);
+    hipLaunchKernelGGL((k_gram0<T>), g, b, 0, st, n, a.ld, R, S, Om, a.seed, a.instance, part, a.counter, small, L);
     hipLaunchKernelGGL(k_small_sigma, dim3(1), dim3(64), 0, st, n, R, a.fp32, small, L);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, A, 1, small, L, L.Lc, part, a.counter);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, a.seed, a.instance, A, 1, small, L, L.Lc, part, a.counter);
     hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, st, n, R, small, L, L.L1, 1);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, A, 0, small, L, L.L1, part, a.counter);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, a.seed, a.instance, A, 0, small, L, L.L1, part, a.counter);
     hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, st, n, R, small, L, L.L2, 0);
-    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, A, 0, small, L, L.L2, part, a.counter);
+    hipLaunchKernelGGL((k_trsm_gram<T>), g, b, 0, st, n, a.ld, R, S, Om, a.seed, a.instance, A, 0, small, L, L.L2, part, a.counter);
     hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(64), 0, st, n, R, small, L, L.L3, 0);
     hipLaunchKernelGGL(k_small_svd, dim3(1), dim3(64), 0, st, R, small, L, a.tau, a.alpha, a.trace_correct, a.lambda,
                        a.err);
@@ -418,7 +420,9 @@ scg_status scg_reconstruct_impl(scg_ctx* c, double* U, double* lambda, double* e
     a.R = c->prm.R;
     a.fp32 = (c->prm.precision == SCG_FP32_STREAM);
     a.S = c->S;
-    a.Om = c->Om;
+    a.Om = (c->prm.omega_mode == 1) ? nullptr : c->Om;
+    a.seed = c->prm.seed;
+    a.instance = (uint64_t)c->prm.instance;
     a.tau = hsc.tau;
     a.alpha = c->alpha_s;
     a.trace_correct = c->prm.trace_correct;

@@ -56,10 +56,38 @@ def test_workspace_size_and_validation():
     bad = [dict(R=0), dict(R=33), dict(n=5, R=6), dict(T=0), dict(beta0=0.0), dict(beta0=-1.0), dict(K=-1.0),
            dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=1), dict(precision=7), dict(n=0),
            dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_grid=-1), dict(spmv_grid=4096),
-           dict(q_mode=1, q_fixed=600, n=10_000)]
+           dict(q_mode=1, q_fixed=600, n=10_000), dict(basis_mode=2), dict(basis_mode=-1), dict(omega_mode=2),
+           dict(basis_mode=1, reorth=2)]
     for kw in bad:
         st, _ = _ws(**dict(kw))
         assert st == _lib.SCG_EINVAL, kw
+
+
+def test_storage_optimal_modes_shrink_the_workspace():
+    # Section 4.2: regenerating the Lanczos basis keeps three n-vectors (plus an
+    # FP64 accumulator) instead of q + 1; a regenerated Omega drops the n x R array.
+    n, R, T = 1_000_000, 10, 100
+    q_max = max(math.ceil(t ** 0.25 * math.log(n)) for t in range(1, T + 1))
+    st0, b0 = _ws(n=n, nnz=5 * n, R=R, T=T)
+    st1, b1 = _ws(n=n, nnz=5 * n, R=R, T=T, basis_mode=1)
+    st2, b2 = _ws(n=n, nnz=5 * n, R=R, T=T, omega_mode=1)
+    st3, b3 = _ws(n=n, nnz=5 * n, R=R, T=T, basis_mode=1, omega_mode=1)
+    assert st0 == st1 == st2 == st3 == _lib.SCG_OK
+    slack = 16 * 256
+    assert b0 - b1 >= 8 * n * (q_max + 1 - 3) - 8 * n - slack
+    assert b0 - b2 >= 8 * n * R - slack
+    assert b0 - b3 >= (b0 - b1) + (b0 - b2) - slack
+    # with the regenerated basis a larger q costs O(q) words of partial sums, not q n-vectors
+    st4, b4 = _ws(n=n, nnz=5 * n, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=120)
+    st5, b5 = _ws(n=n, nnz=5 * n, R=R, T=T, q_mode=1, q_fixed=120)
+    assert st4 == st5 == _lib.SCG_OK
+    assert b5 - b0 >= 8 * n * (120 - q_max)
+    # ... and the same number of bytes at twice the size
+    n2 = 2 * n
+    _, c3 = _ws(n=n2, nnz=5 * n2, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=44)
+    _, c4 = _ws(n=n2, nnz=5 * n2, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=120)
+    _, d3 = _ws(n=n, nnz=5 * n, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=44)
+    assert abs((c4 - c3) - (b4 - d3)) <= slack
 
 
 def test_init_rejects_null_and_misaligned_arguments():
@@ -98,7 +126,8 @@ def test_batch_workspace_size_and_validation():
     st3, b3 = _bws([200, 5000, 20000, 300])
     assert st3 == _lib.SCG_OK and b3 > b
     for sizes, kw in [([200, 5], {}), ([], {}), ([100], dict(reorth=1)), ([100], dict(T=0)),
-                      ([1000], dict(q_mode=1, q_fixed=129)), ([100], dict(precision=3)), ([100], dict(R=33))]:
+                      ([1000], dict(q_mode=1, q_fixed=129)), ([100], dict(precision=3)), ([100], dict(R=33)),
+                      ([100], dict(basis_mode=1)), ([100], dict(omega_mode=1))]:
         st, _ = _bws(sizes, **kw)
         assert st == _lib.SCG_EINVAL, (sizes, kw)
 

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
-from oracle.sketchycgal import approx_min_evec, tridiag_min_eigpair
+from oracle.sketchycgal import approx_min_evec, approx_min_evec_regenerated, tridiag_min_eigpair
 
 
 def _sym(n, rng, spread=1.0):
@@ -84,17 +84,50 @@ def test_fact_rand_lanczos_bound():
     assert fails <= 4
 
 
-def test_breakdown_returns_exact_minimum():
+@pytest.mark.parametrize("regenerated", [False, True])
+def test_breakdown_returns_exact_minimum(regenerated):
     rng = np.random.default_rng(3)
     n = 30
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
     ev = np.repeat([-2.0, 0.5, 3.0], 10)
     M = (Q * ev) @ Q.T
     g = rng.standard_normal(n)
-    xi, v, info = _lanczos_coeffs(M, g, n - 1)
+    if regenerated:
+        xi, v, info = approx_min_evec_regenerated(lambda x: M @ x, g, n - 1)
+    else:
+        xi, v, info = _lanczos_coeffs(M, g, n - 1)
     assert info["broke"] and info["k"] == 3
     assert abs(xi + 2.0) < 1e-12
     assert np.linalg.norm(M @ v + 2.0 * v) < 1e-10
+
+
+@pytest.mark.parametrize("q", [1, 2, 7, 30, 59])
+def test_regenerated_basis_gives_the_stored_basis_result(q):
+    # Section 4.2: the second sweep rebuilds the same vectors, so the Ritz pair is
+    # the stored-basis one; checked also against the Krylov-space Rayleigh-Ritz
+    # solution built from scratch (dense eigh of Q^T M Q).
+    rng = np.random.default_rng(100 + q)
+    n = 60
+    M, ev = _sym(n, rng)
+    g = rng.standard_normal(n)
+    xs, vs, infos = approx_min_evec(lambda x: M @ x, g, q)
+    xr, vr, infor = approx_min_evec_regenerated(lambda x: M @ x, g, q)
+    assert infor["k"] == infos["k"] == q and not infor["broke"]
+    assert xr == xs
+    np.testing.assert_array_equal(infor["omega"], infos["omega"])
+    np.testing.assert_allclose(vr, vs, rtol=0, atol=1e-14)
+    K = np.empty((n, q))
+    x = g / np.linalg.norm(g)
+    for j in range(q):
+        K[:, j] = x
+        x = M @ x
+        x = x / np.linalg.norm(x)
+    Qk, _ = np.linalg.qr(K)
+    w, Y = np.linalg.eigh(Qk.T @ M @ Qk)
+    u = Qk @ Y[:, 0]
+    assert abs(xr - w[0]) < 1e-9 * max(1.0, abs(w[0]))
+    if q < 30:   # explicit Krylov vectors lose rank beyond that
+        assert abs(abs(u @ vr) - 1.0) < 1e-8
 
 
 def test_tridiagonal_solver_against_dense():
