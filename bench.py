@@ -223,6 +223,24 @@ def gather_reference(torch, n: int, count: int, reps: int = 20):
     return count * reps / (e0.elapsed_time(e1) * 1e-3)
 
 
+def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10):
+    """Device-to-device copy rate (read + write bytes per second) of a 1 GiB buffer, HIP events: the
+    bandwidth a plain streaming kernel reaches on this GPU, beside the 8 TB/s vendor figure."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return rate
+
+
 def spmv_line(torch, k: int, precision: str):
     """Lanczos SpMV of workload k alone: autotuned shape, 50 back-to-back launches (HIP events)."""
     import synth
@@ -360,6 +378,7 @@ def main():
     # measured HBM bytes per launch of the shape the autotuner chose (same kernel source only)
     traffic = measured_traffic(2, sum32)
     gref = gather_reference(torch, n, nnz_off)
+    copy_gbs = copy_ceiling(torch)
 
     fp64 = None
     if not args.no_fp64:
@@ -448,6 +467,8 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_us": spmv_ms * 1e3,
+            "copy_ceiling_GBps": copy_gbs,
+            "frac_of_copy_ceiling": achieved / copy_gbs,
             "gathers_per_s": nnz_off / (spmv_ms * 1e-3),
             "uniform_gather_reference_per_s": gref,
             "gathers_over_uniform_reference": nnz_off / (spmv_ms * 1e-3) / gref,
