@@ -33,6 +33,17 @@ Readings of points the paper leaves open (the library takes the same ones):
   R10 Gap and stopping quantities at iteration t use the state before the
       update (p_t, z_t, y_t, beta_t) and xi_t in place of lambda_min(D_t), with
       the factor alpha on xi that the general trace bound alpha implies.
+  R11 General template (Appendix D, alg:full-sketchy-cgal-supp) with A = diag and
+      K a box {lo <= u <= hi}: the projection onto the box is the entrywise
+      clamp (the inequality example of Appendix D.3 prints the negative part
+      of w - b; the projection onto {u <= b} is b + (w - b)_- = min(w, b)).
+      The scaling divides lo and hi by alpha like b.  With H = 0 (trace-bounded
+      set, xi >= 0) the sketch takes RankOneUpdate(0, eta), so it keeps
+      following X_t+1 = (1 - eta) X_t.  The dual step rule of Appendix D.4 has
+      the same bound as eqn sketchy-cgal-dual-step.  The logged infeasibility is
+      dist_K(z_t+1), the feasibility gap of Appendix E.
+  R12 With tr X <= alpha the trace correction of the reconstruction targets the
+      tracked trace tau = tr X_T instead of alpha.
 """
 from __future__ import annotations
 
@@ -62,6 +73,7 @@ class OracleParams:
     trace_correct: bool = True
     instance: int = 0
     reorth: int = 0                 # 0: none (paper); 2: full reorthogonalisation
+    trace_mode: int = 0             # 0: tr X = alpha (alpha Delta_n); 1: tr X <= alpha (Appendix D.2)
 
 
 @dataclasses.dataclass
@@ -79,6 +91,8 @@ class OracleResult:
     Omega: np.ndarray
     log: dict
     vs: list | None = None
+    trace_mode: int = 0
+    dist_K: float | None = None   # general template: dist_K(z_T+1), scaled units
 
     @property
     def objective(self) -> float:
@@ -87,8 +101,9 @@ class OracleResult:
 
     @property
     def infeasibility(self) -> float:
-        """||diag(X) - b|| in the original units."""
-        return self.alpha / self.alpha_s * float(np.linalg.norm(self.z - self.b_s))
+        """||diag(X) - b|| (general template: dist_K(diag X)) in the original units."""
+        d = float(np.linalg.norm(self.z - self.b_s)) if self.dist_K is None else self.dist_K
+        return self.alpha / self.alpha_s * d
 
 
 def lanczos_q(t: int, n: int, q_mode: int = 0, q_fixed: int = 0) -> int:
@@ -297,20 +312,41 @@ _LOG_KEYS = ("t", "q", "k", "xi", "cv", "p", "infeas", "gamma", "gap", "stop_obj
 
 def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: np.ndarray | None = None,
                  record_v: bool = False, start_vectors=None, state0: dict | None = None,
-                 t_stop: int | None = None) -> OracleResult:
-    """SketchyCGAL (alg:sketchy-cgal) for min <C,X> s.t. diag X = b, X in alpha*Delta_n.
+                 t_stop: int | None = None, lo: np.ndarray | None = None,
+                 hi: np.ndarray | None = None) -> OracleResult:
+    """SketchyCGAL (alg:sketchy-cgal) for min <C,X> s.t. diag X = b, X in alpha*Delta_n,
+    and its general template (Appendix D, alg:full-sketchy-cgal-supp) with A = diag.
+
+    General template: given `lo` and/or `hi` (original units; a missing side is
+    unbounded), the constraint is diag X in K = {u : lo <= u <= hi} and every
+    use of b in the iteration becomes a projection onto K (R11); b then only
+    supplies the default alpha = sum(b).  trace_mode = 1 replaces
+    X in alpha*Delta_n by tr X <= alpha, whose linear minimisation returns
+    H = alpha v v^T when xi < 0 and H = 0 otherwise (Appendix D.2).
 
     `start_vectors(t)` may override the Philox start vector of iteration t.
     `state0` = dict(t, z, y, p, S, tau) resumes from the state before
     iteration t (scaled units); iterations run up to `t_stop` (default T).
     Logged per iteration (scaled units): q, Lanczos steps k, xi, v^T C v, p_t,
-    ||z_t - b||, gamma, gap, the two stopping quantities, ||D v - xi v||.
+    dist_K(z_t+1) (= ||z_t+1 - b|| for K = {b}), gamma, gap, the two stopping
+    quantities (K = {b} with tr X = alpha only, else NaN), ||D v - xi v||.
     """
     C = sp.csr_matrix(C, dtype=np.float64)
     n = C.shape[0]
     b = np.asarray(b, dtype=np.float64)
     alpha0 = float(b.sum()) if params.alpha is None else float(params.alpha)
     Cs, bs, alpha, c_F = scale_problem(C, b, alpha0, params.scale)
+    box = lo is not None or hi is not None
+    if box:
+        sK = alpha0 if params.scale else 1.0    # the scaling divides the constraint values by alpha
+        lo_s = np.full(n, -np.inf) if lo is None else np.asarray(lo, dtype=np.float64) / sK
+        hi_s = np.full(n, np.inf) if hi is None else np.asarray(hi, dtype=np.float64) / sK
+
+        def proj(u):   # Euclidean projection onto the box K (Appendix D.3)
+            return np.minimum(np.maximum(u, lo_s), hi_s)
+    else:
+        def proj(u):   # K = {b}
+            return bs
     if Omega is None:
         Omega = gaussian_test_matrix(n, params.R, params.seed, params.instance)
     sketch = NystromSketch(Omega)
@@ -332,38 +368,47 @@ def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: n
     for t in range(t0, (params.T if t_stop is None else t_stop) + 1):
         beta = beta0 * math.sqrt(t + 1.0)
         eta = 2.0 / (t + 1.0)
-        w = y + beta * (z - bs)
+        wK = proj(z + y / beta)              # slack w_t = proj_K(z + y / beta)
+        w = y + beta * (z - wK)              # D = C + diag(w)
         q = lanczos_q(t, n, params.q_mode, params.q_fixed)
         g = start_vectors(t) if start_vectors is not None else start_vector(n, params.seed, t, params.instance)
         xi, v, info = approx_min_evec(lambda x: Cs @ x + w * x, g, q, params.reorth)
         Cv = Cs @ v
         cv = float(np.dot(v, Cv))
         resid = float(np.linalg.norm(Cv + w * v - xi * v))
-        zb = z - bs
-        gap = p + float(np.dot(y + beta * zb, z)) - alpha * xi
-        stop_obj = (p + float(np.dot(y, bs)) + 0.5 * beta * float(np.dot(zb, z + bs)) - alpha * xi) / (1.0 + abs(p))
-        stop_feas = float(np.linalg.norm(zb)) / (1.0 + nb)
+        # linear minimisation over the trace set: H = ha v v^T
+        ha = alpha if (params.trace_mode == 0 or xi < 0.0) else 0.0
+        # surrogate gap <D_t, X_t - H_t> with <D_t, X_t> = p_t + <w, z_t> and <D_t, H_t> = ha xi
+        gap = p + float(np.dot(w, z)) - ha * xi
+        if not box and params.trace_mode == 0:
+            zb = z - bs
+            stop_obj = (p + float(np.dot(y, bs)) + 0.5 * beta * float(np.dot(zb, z + bs)) - alpha * xi) / (1.0 + abs(p))
+            stop_feas = float(np.linalg.norm(zb)) / (1.0 + nb)
+        else:
+            stop_obj = stop_feas = math.nan
         # primal state, objective tracker and dual (alg:sketchy-cgal; Section 6.2)
-        p = (1.0 - eta) * p + eta * alpha * cv
-        z = (1.0 - eta) * z + eta * alpha * (v * v)
-        zb = z - bs
+        p = (1.0 - eta) * p + eta * ha * cv
+        z = (1.0 - eta) * z + eta * ha * (v * v)
+        zb = z - proj(z + y / (beta0 * math.sqrt(t + 2.0)))   # z - w_bar
         r2 = float(np.dot(zb, zb))
+        infeas = math.sqrt(r2) if not box else float(np.linalg.norm(z - proj(z)))
         gamma = dual_step_size(r2, t, alpha, beta0)
         y_new = y + gamma * zb
         if np.linalg.norm(y_new) > params.K:
             gamma = 0.0
         else:
             y = y_new
-        # sketch: RankOneUpdate(sqrt(alpha) v, eta)
-        sketch.rank_one_update(math.sqrt(alpha) * v, eta)
-        for key, val in zip(_LOG_KEYS, (t, q, info["k"], xi, cv, p, math.sqrt(r2), gamma, gap, stop_obj,
+        # sketch: RankOneUpdate(sqrt(ha) v, eta), i.e. the sketch follows X <- (1-eta) X + eta H
+        sketch.rank_one_update(math.sqrt(ha) * v, eta)
+        for key, val in zip(_LOG_KEYS, (t, q, info["k"], xi, cv, p, infeas, gamma, gap, stop_obj,
                                         stop_feas, resid, beta, eta)):
             log[key].append(val)
         if record_v:
             vs.append(v.copy())
     log = {k: np.array(v) for k, v in log.items()}
     return OracleResult(n=n, alpha=alpha0, c_F=c_F, alpha_s=alpha, b_s=bs, p=p, z=z, y=y, S=sketch.S,
-                        tau=sketch.tau, Omega=sketch.Omega, log=log, vs=vs)
+                        tau=sketch.tau, Omega=sketch.Omega, log=log, vs=vs, trace_mode=params.trace_mode,
+                        dist_K=float(np.linalg.norm(z - proj(z))) if box else None)
 
 
 def state_of(res: OracleResult, t_next: int) -> dict:
@@ -372,6 +417,8 @@ def state_of(res: OracleResult, t_next: int) -> dict:
 
 
 def reconstruct_result(res: OracleResult, trace_correct: bool = True, storage: str = "f64"):
-    """Reconstruct the final sketch of a run; U, Lambda in scaled units (X_hat = U diag(lam) U^T)."""
-    return nystrom_reconstruct(res.S, res.Omega, res.tau, alpha=res.alpha_s if trace_correct else None,
+    """Reconstruct the final sketch of a run; U, Lambda in scaled units (X_hat = U diag(lam) U^T).
+    The trace correction targets alpha, or the tracked trace tau of X_T when tr X <= alpha (R12)."""
+    target = res.alpha_s if res.trace_mode == 0 else res.tau
+    return nystrom_reconstruct(res.S, res.Omega, res.tau, alpha=target if trace_correct else None,
                                storage=storage)
