@@ -14,6 +14,12 @@
  * Nystrom sketch S = X Omega (Section 5).  C is touched only through sparse
  * matrix-vector products (primitives 1 and 2).
  *
+ * The same engine runs the general template of Appendix D (eqn
+ * general-problem, alg:full-sketchy-cgal-supp) with the diagonal constraint
+ * map: diag(X) in a box K = {lo <= u <= hi} (params.constraint_set = 1 and
+ * sketchycgal_set_constraints), and tr X <= alpha in place of tr X = alpha
+ * (params.trace_mode = 1).  Equality rows have lo_i = hi_i.
+ *
  * Conventions for every entry point:
  *   - Arrays marked "device" are hipMalloc'd (or torch CUDA) pointers on the
  *     current HIP device; arrays marked "host" are ordinary host memory.
@@ -89,6 +95,15 @@ typedef struct {
                                1 = regenerated from the Philox counters wherever it is used
                                (no n x R array; the caller may not pass omega).  Singleton
                                engine only                                                    */
+    int32_t  trace_mode;    /* 0: tr X = alpha (the set alpha Delta_n of eqn model-problem);
+                               1: tr X <= alpha: the linear minimisation returns H = alpha
+                               v v^T when xi < 0 and H = 0 otherwise (Appendix D.2).
+                               Singleton engine only                                          */
+    int32_t  constraint_set;/* 0: diag X = b; 1: lo <= diag X <= hi (Appendix D.3; every use
+                               of b in the iteration becomes the projection onto the box),
+                               bounds from sketchycgal_set_constraints (until then lo = hi =
+                               b).  b then only gives the default alpha = sum(b).  Singleton
+                               engine only                                                    */
 } scg_params;
 
 /* One record per iteration t, in scaled units (see file comment).  Gap and
@@ -99,11 +114,11 @@ typedef struct {
     double xi;                /* Ritz value (approximate lambda_min(D_t))                          */
     double cv;                /* v^T C v                                                           */
     double p;                 /* p_{t+1} = <C, X_{t+1}>                                            */
-    double infeas;            /* ||z_{t+1} - b||                                                   */
+    double infeas;            /* ||z_{t+1} - b||; box constraints: dist_K(z_{t+1})                 */
     double gamma;             /* dual step taken (0 when the K guard refused it)                   */
-    double gap;               /* surrogate duality gap g_t                                         */
-    double stop_obj;          /* relative-gap stopping quantity                                    */
-    double stop_feas;         /* ||z_t - b|| / (1 + ||b||)                                         */
+    double gap;               /* surrogate duality gap g_t = <D_t, X_t - H_t>                      */
+    double stop_obj;          /* relative-gap stopping quantity (NaN unless diag X = b, tr X = a)  */
+    double stop_feas;         /* ||z_t - b|| / (1 + ||b||)      (NaN unless diag X = b, tr X = a)  */
     double resid;             /* ||D_t v - xi v||                                                  */
     double beta, eta;
 } scg_iter_log;
@@ -114,7 +129,7 @@ typedef struct {
     int32_t t_done;           /* iterations completed                       */
     int32_t status_flags;     /* bit0: NaN/Inf seen                         */
     double objective;         /* <C, X>                                     */
-    double infeasibility;     /* ||diag X - b||                             */
+    double infeasibility;     /* ||diag X - b|| (box constraints: dist_K)   */
     double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
     int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction               */
     int32_t spmv_segments;    /* column segments of the SpMV                                   */
@@ -153,6 +168,16 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
                             const double* b, const double* omega, void* workspace,
                             size_t ws_bytes, void* stream);
 
+/* Box constraint set K = {u : lo <= u <= hi} of the general template
+ * (Appendix D.3) for a context initialised with params.constraint_set = 1.
+ *   lo, hi   device double[n] in original units (the scaling divides them by
+ *            alpha like b), or NULL for an unbounded side; -inf / +inf entries
+ *            are allowed; copied, may be freed after the call returns.
+ * Must be called before the first sketchycgal_step (SCG_ESTATE otherwise).
+ * SCG_EINVAL if constraint_set != 1, or any lo_i > hi_i or NaN bound
+ * (synchronises the stream once for that check). */
+scg_status sketchycgal_set_constraints(scg_ctx* ctx, const double* lo, const double* hi);
+
 /* Enqueue `iters` iterations of alg:sketchy-cgal (loop body: ApproxMinEvec by
  * randomized Lanczos, z, y and sketch updates).  Asynchronous: never
  * synchronises.  SCG_ESTATE if it would run past T. */
@@ -160,7 +185,8 @@ scg_status sketchycgal_step(scg_ctx* ctx, int32_t iters);
 
 /* NystromSketch.Reconstruct (alg:nystrom-sketch-supp) of the current sketch,
  * in FP64 on the device, with the optional trace correction of
- * alg:sketchy-cgal.  X_hat = U diag(lambda) U^T approximates X in SCALED
+ * alg:sketchy-cgal (to alpha; with trace_mode = 1 to the tracked trace
+ * tau = tr X_T).  X_hat = U diag(lambda) U^T approximates X in SCALED
  * units (multiply lambda by alpha/alpha_scaled for the original X).
  *   U       device double[n*R] column-major (column j contiguous), orthonormal
  *   lambda  device double[R], nonincreasing, >= 0 (trace-corrected if enabled)

@@ -18,7 +18,8 @@ class scg_params(C.Structure):
         ("scale", C.c_int32), ("trace_correct", C.c_int32), ("reorth", C.c_int32),
         ("precision", C.c_int32), ("instance", C.c_int32), ("matrix_format", C.c_int32),
         ("autotune", C.c_int32), ("segments", C.c_int32), ("spmv_lanes", C.c_int32), ("spmv_grid", C.c_int32),
-        ("basis_mode", C.c_int32), ("omega_mode", C.c_int32),
+        ("basis_mode", C.c_int32), ("omega_mode", C.c_int32), ("trace_mode", C.c_int32),
+        ("constraint_set", C.c_int32),
     ]
 
 
@@ -44,7 +45,7 @@ EXPORTS = [
     "scg_default_params", "scg_workspace_size", "sketchycgal_init", "sketchycgal_step",
     "sketchycgal_reconstruct", "sketchycgal_log", "sketchycgal_summary", "sketchycgal_get_state",
     "sketchycgal_set_state", "sketchycgal_lanczos_coeffs", "sketchycgal_apply", "sketchycgal_time_spmv",
-    "sketchycgal_destroy", "scg_status_string", "sketchycgal_round",
+    "sketchycgal_destroy", "scg_status_string", "sketchycgal_round", "sketchycgal_set_constraints",
     "scg_batch_workspace_size", "sketchycgal_batch_init", "sketchycgal_batch_step", "sketchycgal_batch_log",
     "sketchycgal_batch_summary", "sketchycgal_batch_get_state", "sketchycgal_batch_set_state", "sketchycgal_batch_reconstruct",
     "sketchycgal_batch_destroy", "sketchycgal_batch_round",
@@ -88,6 +89,7 @@ def load() -> C.CDLL:
     lib.sketchycgal_batch_set_state.argtypes = [vp, i32, i32, vp, vp, vp, C.c_double, C.c_double]
     lib.sketchycgal_batch_reconstruct.argtypes = [vp, i32, vp, vp, vp]
     lib.sketchycgal_round.argtypes = [vp, vp, vp, P(C.c_double), P(i32)]
+    lib.sketchycgal_set_constraints.argtypes = [vp, vp, vp]
     lib.sketchycgal_batch_round.argtypes = [vp, i32, vp, vp, P(C.c_double), P(i32)]
     lib.sketchycgal_batch_destroy.argtypes = [vp]
     lib.sketchycgal_batch_destroy.restype = None

@@ -39,6 +39,8 @@ class Params:
     spmv_grid: int = 0            # SpMV workgroups: 0 auto, or a cap
     basis_mode: int = 0           # 0: keep the Lanczos basis; 1: three vectors, basis regenerated
     omega_mode: int = 0           # 0: store the test matrix; 1: regenerate it from its counters
+    trace_mode: int = 0           # 0: tr X = alpha; 1: tr X <= alpha
+    constraint_set: int = 0       # 0: diag X = b; 1: lo <= diag X <= hi (set_constraints)
 
     def to_c(self) -> _lib.scg_params:
         p = _lib.scg_params()
@@ -48,6 +50,7 @@ class Params:
         p.matrix_format, p.autotune, p.segments = self.matrix_format, self.autotune, self.segments
         p.spmv_lanes, p.spmv_grid = self.spmv_lanes, self.spmv_grid
         p.basis_mode, p.omega_mode = self.basis_mode, self.omega_mode
+        p.trace_mode, p.constraint_set = self.trace_mode, self.constraint_set
         p.precision = {"fp64": _lib.SCG_FP64, "fp32": _lib.SCG_FP32_STREAM}[self.precision]
         return p
 
@@ -106,6 +109,12 @@ class SketchyCGAL:
         if ctx is not None and ctx.value:
             self.lib.sketchycgal_destroy(ctx)
             self.ctx = None
+
+    def set_constraints(self, lo=None, hi=None):
+        """Box constraint set lo <= diag X <= hi (original units; None = unbounded side)."""
+        lo_t = None if lo is None else _dev(lo, torch.float64, self.device)
+        hi_t = None if hi is None else _dev(hi, torch.float64, self.device)
+        check(self.lib.sketchycgal_set_constraints(self.ctx, _ptr(lo_t), _ptr(hi_t)), "sketchycgal_set_constraints")
 
     def step(self, iters: int = 1):
         check(self.lib.sketchycgal_step(self.ctx, iters), "sketchycgal_step")

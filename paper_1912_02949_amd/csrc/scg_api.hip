@@ -44,7 +44,7 @@ int qmax_for(const scg_params& p, int64_t n) {
 size_t elem_size(const scg_params& p) { return p.precision == SCG_FP32_STREAM ? 4 : 8; }
 
 struct Layout {
-    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, racc, total;
+    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, total;
     size_t recon_bytes;
 };
 
@@ -72,13 +72,15 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.S = take(es * ld * R);
     L.rb = take(sizeof(int2) * (size_t)kSegMax * (n + 2));
     L.sc = take(sizeof(DevScalars));
-    const size_t pw = 14 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
+    const size_t pw = 15 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
     L.part = take(8 * (size_t)kGMax * pw);
     L.counter = take(256);
     L.logs = take(sizeof(scg_iter_log) * (size_t)p.T);
     L.recon_bytes = 8 * scg_recon_scratch_doubles(n, p.R);
     L.recon = take(L.recon_bytes);
     L.racc = take(p.basis_mode == 1 ? 8 * ld : 0);
+    L.lo = take(p.constraint_set == 1 ? 8 * (size_t)n : 0);   // box constraint set, scaled
+    L.hi = take(p.constraint_set == 1 ? 8 * (size_t)n : 0);
     L.total = off;
     return L;
 }
@@ -97,6 +99,9 @@ Prob<T> prob(scg_ctx* c) {
     P.cval = c->cval;
     P.dC = c->dC;
     P.b = c->b;
+    P.lo = c->lo;
+    P.hi = c->hi;
+    P.trace_mode = c->prm.trace_mode;
     P.z = c->z;
     P.y = c->y;
     P.s = (T*)c->s;
@@ -119,7 +124,7 @@ Prob<T> prob(scg_ctx* c) {
     P.p_ritz = pp + (size_t)kGMax * 8;
     P.p_obj = pp + (size_t)kGMax * (9 + kRMax);
     P.p_primal = pp + (size_t)kGMax * (11 + kRMax);
-    P.p_h = pp + (size_t)kGMax * (14 + kRMax);
+    P.p_h = pp + (size_t)kGMax * (15 + kRMax);
     P.G = c->G;
     P.Gs = c->Gs;
     P.logs = c->logs;
@@ -189,6 +194,7 @@ IterArgs iter_args(scg_ctx* c, int t) {
     it.t = t;
     it.q = q_for(c->prm, c->n, t);
     it.beta = c->prm.beta0 * std::sqrt(t + 1.0);
+    it.beta_next = c->prm.beta0 * std::sqrt(t + 2.0);
     it.eta = 2.0 / (t + 1.0);
     it.alpha = c->alpha_s;
     it.beta0 = c->prm.beta0;
@@ -237,6 +243,21 @@ void enqueue_iteration(scg_ctx* c, int t) {
 }
 
 // ------------------------------------------------------------- init kernels
+// Box constraint set in scaled units; err bit 8 for lo > hi, a NaN bound or an
+// empty side (lo = +inf or hi = -inf).
+__global__ __launch_bounds__(kBlock) void k_set_box(int64_t n, const double* lo, const double* hi, double inv_alpha,
+                                                    double* lo_s, double* hi_s, DevScalars* sc) {
+    int err = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double l = lo ? lo[i] : -INFINITY;
+        const double h = hi ? hi[i] : INFINITY;
+        if (!(l <= h) || l == INFINITY || h == -INFINITY) err = 8;
+        lo_s[i] = l * inv_alpha;
+        hi_s[i] = h * inv_alpha;
+    }
+    if (err) atomicOr(&sc->err, err);
+}
+
 __global__ __launch_bounds__(kBlock) void k_validate(int64_t n, const int64_t* rp, const int32_t* col,
                                                      const double* val, const double* b, int32_t* cnt,
                                                      double* dCraw, DevScalars* sc, double* part,
@@ -638,6 +659,10 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     hipLaunchKernelGGL((k_scatter<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, c->rp,
                        c->col, (T*)c->val, dCraw, c->dC, c->b, inv_cF, inv_alpha, c->fmt);
     HIP_TRY(hipGetLastError());
+    if (c->lo) {   // K = {b} until sketchycgal_set_constraints
+        HIP_TRY(hipMemcpyAsync(c->lo, c->b, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->hi, c->b, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+    }
     if (c->prm.omega_mode == 1) {
         // Omega is generated from Philox wherever it is used
     } else if (omega) {
@@ -688,6 +713,8 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (p->basis_mode != 0 && p->basis_mode != 1) return false;
     if (p->basis_mode == 1 && p->reorth != 0) return false;   // reorthogonalisation needs the stored basis
     if (p->omega_mode != 0 && p->omega_mode != 1) return false;
+    if (p->trace_mode != 0 && p->trace_mode != 1) return false;
+    if (p->constraint_set != 0 && p->constraint_set != 1) return false;
     return true;
 }
 
@@ -718,6 +745,8 @@ void scg_default_params(scg_params* p) {
     p->spmv_grid = 0;
     p->basis_mode = 0;
     p->omega_mode = 0;
+    p->trace_mode = 0;
+    p->constraint_set = 0;
 }
 
 scg_status scg_workspace_size(const scg_params* p, int64_t n, int64_t nnz, size_t* bytes) {
@@ -761,6 +790,8 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->v = base + L.v;
     c->Om = base + L.Om;
     c->racc = (p->basis_mode == 1) ? (double*)(base + L.racc) : nullptr;
+    c->lo = (p->constraint_set == 1) ? (double*)(base + L.lo) : nullptr;
+    c->hi = (p->constraint_set == 1) ? (double*)(base + L.hi) : nullptr;
     c->S = base + L.S;
     c->rb = (int32_t*)(base + L.rb);
     c->rb_cap = (size_t)kSegMax * (n + 2);
@@ -790,6 +821,28 @@ scg_status sketchycgal_step(scg_ctx* c, int32_t iters) {
         c->t_next++;
     }
     HIP_TRY(hipGetLastError());
+    return SCG_OK;
+}
+
+scg_status sketchycgal_set_constraints(scg_ctx* c, const double* lo, const double* hi) {
+    if (!c || c->prm.constraint_set != 1 || !c->lo) return SCG_EINVAL;
+    if (c->t_next != 1) return SCG_ESTATE;
+    const int64_t n = c->n;
+    const double inv_alpha = c->prm.scale ? 1.0 / c->alpha_orig : 1.0;   // as b (k_scatter)
+    const int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+    HIP_TRY(hipMemsetAsync(&c->sc->err, 0, sizeof(int32_t), c->stream));
+    hipLaunchKernelGGL(k_set_box, dim3(g), dim3(kBlock), 0, c->stream, n, lo, hi, inv_alpha, c->lo, c->hi, c->sc);
+    HIP_TRY(hipGetLastError());
+    int32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, &c->sc->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (err != 0) {   // back to K = {b}
+        HIP_TRY(hipMemcpyAsync(c->lo, c->b, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->hi, c->b, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemsetAsync(&c->sc->err, 0, sizeof(int32_t), c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return SCG_EINVAL;
+    }
     return SCG_OK;
 }
 

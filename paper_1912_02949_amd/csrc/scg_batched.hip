@@ -1374,6 +1374,7 @@ bool bparams_ok(const scg_params* p, int ninst, const int64_t* inst_n) {
     if (p->precision != SCG_FP64 && p->precision != SCG_FP32_STREAM) return false;
     if (p->matrix_format != 0 && p->matrix_format != 1) return false;
     if (p->basis_mode != 0 || p->omega_mode != 0) return false;   // the batch keeps both in HBM
+    if (p->trace_mode != 0 || p->constraint_set != 0) return false;   // the MaxCut model only
     int64_t total = 0;
     for (int k = 0; k < ninst; ++k) {
         const int64_t n = inst_n[k];

@@ -53,6 +53,9 @@ struct Prob {
     double cval;          // the common (absolute) off-diagonal value, FMT_PAT / FMT_SGN
     const double* dC;     // diagonal of C (scaled)
     const double* b;      // scaled b
+    const double* lo;     // box constraint set (scaled), or null: K = {b}
+    const double* hi;
+    int trace_mode;       // 0: tr X = alpha; 1: tr X <= alpha
     double* z;
     double* y;
     T* s;                 // diagonal shift of D: dC + y + beta (z - b)
@@ -74,7 +77,7 @@ struct Prob {
     double* p_upd;        // k_lupdate / k_reorth_apply, G x 1
     double* p_ritz;       // k_ritz,        G  x (RB + 1)
     double* p_obj;        // k_spmv OBJ,    Gs x 2
-    double* p_primal;     // k_primal,      G  x 3
+    double* p_primal;     // k_primal,      G  x 4
     double* p_h;          // k_reorth_dot,  G  x (step + 1)
     int G;                // workgroups of the vector kernels
     int Gs;               // workgroups of the SpMV kernels
@@ -133,6 +136,8 @@ struct scg_ctx {
     scg_iter_log* logs;
     double* recon;   // reconstruction scratch (n x R FP64 and small matrices)
     double* racc;    // FP64 Ritz accumulator (regenerated basis), else null
+    double* lo;      // box constraint set, scaled (constraint_set = 1), else null
+    double* hi;
     size_t recon_bytes;
 };
 

@@ -36,12 +36,13 @@ namespace scg {
 enum SpmvMode { SPMV_LANCZOS = 0, SPMV_OBJ = 1, SPMV_APPLY = 2 };
 
 // Partial-sum widths of the producers.
-constexpr int kWPrep = 6, kWSpmv = 1, kWUpd = 1, kWObj = 2, kWPrimal = 3;
+constexpr int kWPrep = 6, kWSpmv = 1, kWUpd = 1, kWObj = 2, kWPrimal = 4;
 
 struct IterArgs {
     int t;
     int q;
     double beta, eta, alpha, beta0, K;
+    double beta_next;     // beta_{t+1} = beta0 sqrt(t + 2), for the slack of the dual update
     uint64_t seed;
     uint64_t instance;
 };
@@ -657,7 +658,12 @@ __global__ __launch_bounds__(kBlock) void k_ritz_fin(DevScalars* sc, const doubl
     }
 }
 
+// Euclidean projection onto the box [lo, hi] (Appendix D.3), entrywise.
+__device__ __forceinline__ double box_proj(double u, double lo, double hi) { return fmin(fmax(u, lo), hi); }
+
 // Shift, start vector, and partial sums of the state before the update.
+// Box constraint set: the shift uses the slack w = proj_K(z + y / beta) in
+// place of b (alg:full-sketchy-cgal-supp).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
     DevScalars* sc = P.sc;
@@ -670,20 +676,25 @@ __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
     SCG_FOR_QUADS(n) {
         const int64_t r = 4 * qd;
         const int m = quad_rows(r, n);
-        double g[4], z4[4], y4[4], b4[4], d4[4], s4[4];
+        double g[4], z4[4], y4[4], b4[4], d4[4], s4[4], lo4[4], hi4[4];
         normal4(it.seed, (uint64_t)qd, (uint64_t)it.t, it.instance, 0ull, g);
         ld4(P.z + r, m, z4);
         ld4(P.y + r, m, y4);
         ld4(P.b + r, m, b4);
         ld4(P.dC + r, m, d4);
+        if (P.lo) {
+            ld4(P.lo + r, m, lo4);
+            ld4(P.hi + r, m, hi4);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const double zb = z4[j] - b4[j];
-            s4[j] = d4[j] + (y4[j] + it.beta * zb);
+            const double zw = P.lo ? z4[j] - box_proj(z4[j] + y4[j] / it.beta, lo4[j], hi4[j]) : zb;
+            s4[j] = d4[j] + (y4[j] + it.beta * zw);
             if (j < m) {
                 a[1] += y4[j] * b4[j];
                 a[2] += zb * (z4[j] + b4[j]);
-                a[3] += (y4[j] + it.beta * zb) * z4[j];
+                a[3] += (y4[j] + it.beta * zw) * z4[j];
                 a[4] += zb * zb;
                 a[5] += b4[j] * b4[j];
             } else {
@@ -698,29 +709,46 @@ __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
     write_partials<kWPrep>(a, P.p_prep);
 }
 
-// z update; partial sums of ||z - b||^2 (and y^T y, y^T (z - b) for the K guard).
+// z update with H = ha v v^T (ha = alpha, or 0 when tr X <= alpha and xi >= 0);
+// partial sums of ||z - w_bar||^2 with the slack w_bar = b, or proj_K(z + y / beta_{t+1})
+// for a box, (y^T y, y^T (z - w_bar) for the K guard) and dist_K(z)^2 (box).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_primal(Prob<T> P, IterArgs it) {
     DevScalars* sc = P.sc;
     const double iv = sc->inv_vnorm;
-    const double ea = it.eta * it.alpha;
+    const bool hon = (P.trace_mode == 0) || (sc->xi < 0.0);
+    const double ea = hon ? it.eta * it.alpha : 0.0;
     const double keep = 1.0 - it.eta;
     const bool guard = isfinite(it.K);
+    const bool box = P.lo != nullptr;
     const int64_t n = P.n;
-    double a[kWPrimal] = {0, 0, 0};
+    double a[kWPrimal] = {0, 0, 0, 0};
     SCG_FOR_QUADS(n) {
         const int64_t r = 4 * qd;
         const int m = quad_rows(r, n);
-        double v4[4], z4[4], b4[4], y4[4];
+        double v4[4], z4[4], b4[4], y4[4], lo4[4], hi4[4];
         ld4(P.v + r, m, v4);
         ld4(P.z + r, m, z4);
         ld4(P.b + r, m, b4);
-        if (guard) ld4(P.y + r, m, y4);
+        if (guard || box) ld4(P.y + r, m, y4);
+        if (box) {
+            ld4(P.lo + r, m, lo4);
+            ld4(P.hi + r, m, hi4);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const double vh = v4[j] * iv;
             z4[j] = keep * z4[j] + ea * (vh * vh);
-            const double dd = (j < m) ? z4[j] - b4[j] : 0.0;
+            double dd = 0.0;
+            if (j < m) {
+                if (box) {
+                    dd = z4[j] - box_proj(z4[j] + y4[j] / it.beta_next, lo4[j], hi4[j]);
+                    const double dk = z4[j] - box_proj(z4[j], lo4[j], hi4[j]);
+                    a[3] += dk * dk;
+                } else {
+                    dd = z4[j] - b4[j];
+                }
+            }
             a[0] += dd * dd;
             if (guard) {
                 a[1] += y4[j] * y4[j];
@@ -741,24 +769,29 @@ __global__ __launch_bounds__(kBlock) void k_primal(Prob<T> P, IterArgs it) {
     }
 }
 
-// Dual step size (eqn sketchy-cgal-dual-step), K guard, trackers and log;
-// y <- y + gamma (z - b);  S <- (1-eta) S + eta alpha v_hat (v_hat^T Omega).
+// Dual step size (eqn sketchy-cgal-dual-step; the same bound in Appendix D.4),
+// K guard, trackers and log; y <- y + gamma (z - w_bar) (w_bar as in k_primal);
+// S <- (1-eta) S + eta ha v_hat (v_hat^T Omega).
 template <typename T, int RB>
 __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) {
     DevScalars* sc = P.sc;
     const int64_t n = P.n;
+    const bool box = P.lo != nullptr;
     int64_t qlo, qhi;
     split_range((n + 3) / 4, xcd_lid(), gridDim.x, qlo, qhi);
     int64_t qd = qlo + threadIdx.x;
-    double y4[4], z4[4], b4[4], v4[4];
-    if (qd < qhi) {   // first quad in flight before the reduction
-        const int64_t r = 4 * qd;
-        const int m = quad_rows(r, n);
+    double y4[4], z4[4], b4[4], v4[4], lo4[4], hi4[4];
+    auto load = [&](int64_t r, int m) {
         ld4(P.y + r, m, y4);
         ld4(P.z + r, m, z4);
         ld4(P.b + r, m, b4);
         ld4(P.v + r, m, v4);
-    }
+        if (box) {
+            ld4(P.lo + r, m, lo4);
+            ld4(P.hi + r, m, hi4);
+        }
+    };
+    if (qd < qhi) load(4 * qd, quad_rows(4 * qd, n));   // first quad in flight before the reduction
     double tot[kWPrimal];
     reduce_partials<kWPrimal>(P.p_primal, P.G, tot);
     const double r2 = tot[0];
@@ -769,15 +802,19 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
         if (sqrt(fmax(ny2, 0.0)) > it.K) gamma = 0.0;
     }
     const double iv = sc->inv_vnorm;
-    const double ea = it.eta * it.alpha;
+    const bool hon = (P.trace_mode == 0) || (sc->xi < 0.0);
+    const double ea = hon ? it.eta * it.alpha : 0.0;
     const double keep = 1.0 - it.eta;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->gamma_eff = gamma;
         const double p_old = sc->p;
         const double xi = sc->xi;
-        const double stop_obj = (p_old + sc->d_yb + 0.5 * it.beta * sc->d_zz - it.alpha * xi) / (1.0 + fabs(p_old));
-        const double gap = p_old + sc->d_gapdot - it.alpha * xi;
-        const double stop_feas = sqrt(sc->d_zb2) / (1.0 + sqrt(sc->b2));
+        // the stopping quantities are those of the model problem (diag X = b, tr X = alpha)
+        const bool model = !box && P.trace_mode == 0;
+        const double stop_obj =
+            model ? (p_old + sc->d_yb + 0.5 * it.beta * sc->d_zz - it.alpha * xi) / (1.0 + fabs(p_old)) : NAN;
+        const double gap = p_old + sc->d_gapdot - (hon ? it.alpha * xi : 0.0);
+        const double stop_feas = model ? sqrt(sc->d_zb2) / (1.0 + sqrt(sc->b2)) : NAN;
         const double p_new = keep * p_old + ea * sc->cv;
         sc->p = p_new;
         sc->tau = keep * sc->tau + ea * (sc->vnorm2 * iv * iv);
@@ -791,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
             L.xi = xi;
             L.cv = sc->cv;
             L.p = p_new;
-            L.infeas = sqrt(r2);
+            L.infeas = box ? sqrt(tot[3]) : sqrt(r2);
             L.gamma = gamma;
             L.gap = gap;
             L.stop_obj = stop_obj;
@@ -812,7 +849,8 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
         const int m = quad_rows(r, n);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            y4[j] += gamma * (z4[j] - b4[j]);
+            const double wb = box ? box_proj(z4[j] + y4[j] / it.beta_next, lo4[j], hi4[j]) : b4[j];
+            y4[j] += gamma * (z4[j] - wb);
             v4[j] = ea * (v4[j] * iv);
         }
         st4(P.y + r, m, y4);
@@ -828,14 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
                 st4(P.S + (size_t)c * P.ld + r, m, s4[c]);
             }
         qd += kBlock;
-        if (qd < qhi) {
-            const int64_t r2 = 4 * qd;
-            const int m2 = quad_rows(r2, n);
-            ld4(P.y + r2, m2, y4);
-            ld4(P.z + r2, m2, z4);
-            ld4(P.b + r2, m2, b4);
-            ld4(P.v + r2, m2, v4);
-        }
+        if (qd < qhi) load(4 * qd, quad_rows(4 * qd, n));
     }
 }
 

@@ -424,7 +424,7 @@ scg_status scg_reconstruct_impl(scg_ctx* c, double* U, double* lambda, double* e
     a.seed = c->prm.seed;
     a.instance = (uint64_t)c->prm.instance;
     a.tau = hsc.tau;
-    a.alpha = c->alpha_s;
+    a.alpha = (c->prm.trace_mode == 1) ? hsc.tau : c->alpha_s;   // trace target: tr X_T when tr X <= alpha
     a.trace_correct = c->prm.trace_correct;
     a.scratch = c->recon;
     a.counter = c->counter;

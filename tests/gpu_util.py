@@ -34,7 +34,7 @@ def make_solver(inst: synth.MaxCutInstance, omega=None, **kw):
 def oracle_params(**kw) -> OracleParams:
     kw = dict(kw)
     for key in ("precision", "matrix_format", "segments", "autotune", "spmv_lanes", "spmv_grid",
-                "basis_mode", "omega_mode"):
+                "basis_mode", "omega_mode", "constraint_set"):
         kw.pop(key, None)
     alpha = kw.pop("alpha", 0.0)
     op = OracleParams(**{k: v for k, v in kw.items() if k in {f.name for f in dataclasses.fields(OracleParams)}})
@@ -45,8 +45,8 @@ def oracle_params(**kw) -> OracleParams:
     return op
 
 
-def oracle_run(inst, **kw):
-    return sketchy_cgal(inst.to_scipy(), inst.b, oracle_params(**kw))
+def oracle_run(inst, lo=None, hi=None, **kw):
+    return sketchy_cgal(inst.to_scipy(), inst.b, oracle_params(**kw), lo=lo, hi=hi)
 
 
 def oracle_snapshots(inst, ts, **kw):

@@ -57,7 +57,7 @@ def test_workspace_size_and_validation():
            dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=1), dict(precision=7), dict(n=0),
            dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_grid=-1), dict(spmv_grid=4096),
            dict(q_mode=1, q_fixed=600, n=10_000), dict(basis_mode=2), dict(basis_mode=-1), dict(omega_mode=2),
-           dict(basis_mode=1, reorth=2)]
+           dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=2)]
     for kw in bad:
         st, _ = _ws(**dict(kw))
         assert st == _lib.SCG_EINVAL, kw
@@ -88,6 +88,16 @@ def test_storage_optimal_modes_shrink_the_workspace():
     _, c4 = _ws(n=n2, nnz=5 * n2, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=120)
     _, d3 = _ws(n=n, nnz=5 * n, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=44)
     assert abs((c4 - c3) - (b4 - d3)) <= slack
+
+
+def test_box_constraint_set_adds_two_vectors():
+    n = 100_000
+    st0, b0 = _ws(n=n, nnz=6 * n)
+    st1, b1 = _ws(n=n, nnz=6 * n, constraint_set=1, trace_mode=1)
+    assert st0 == st1 == _lib.SCG_OK
+    assert 16 * n <= b1 - b0 <= 16 * n + 2 * 256
+    lib = _lib.load()
+    assert lib.sketchycgal_set_constraints(None, None, None) == _lib.SCG_EINVAL
 
 
 def test_init_rejects_null_and_misaligned_arguments():
@@ -127,7 +137,8 @@ def test_batch_workspace_size_and_validation():
     assert st3 == _lib.SCG_OK and b3 > b
     for sizes, kw in [([200, 5], {}), ([], {}), ([100], dict(reorth=1)), ([100], dict(T=0)),
                       ([1000], dict(q_mode=1, q_fixed=129)), ([100], dict(precision=3)), ([100], dict(R=33)),
-                      ([100], dict(basis_mode=1)), ([100], dict(omega_mode=1))]:
+                      ([100], dict(basis_mode=1)), ([100], dict(omega_mode=1)), ([100], dict(trace_mode=1)),
+                      ([100], dict(constraint_set=1))]:
         st, _ = _bws(sizes, **kw)
         assert st == _lib.SCG_EINVAL, (sizes, kw)
 

@@ -1,0 +1,186 @@
+"""General template on the GPU (Appendix D, alg:full-sketchy-cgal-supp) with the
+diagonal constraint map: a box constraint set K = {lo <= diag X <= hi} and the
+trace-bounded set tr X <= alpha, against the oracle's general template (pinned
+in test_oracle_general.py) and against the equality model it contains.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import need_gpu, make_solver, oracle_run, rel, maxrel, announce
+from oracle.sketchycgal import reconstruct_result
+
+pytestmark = pytest.mark.gpu
+
+SEED1 = synth.CONFIG_SEEDS[1]
+EXACT = ("p", "xi", "cv", "gamma", "gap", "k", "flags", "infeas")
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.config_instance(1)
+
+
+def _boxes(inst, which):
+    n = inst.n
+    rng = np.random.default_rng(77)
+    if which == "upper":          # diag X <= 1
+        return None, np.ones(n)
+    if which == "lower":          # diag X >= 1
+        return np.ones(n), None
+    lo = rng.uniform(0.5, 1.0, n)  # two-sided, some rows equalities
+    hi = lo + rng.uniform(0.0, 1.0, n) * (rng.random(n) < 0.8)
+    return lo, hi
+
+
+def _solver(inst, lo=None, hi=None, boxed=True, **kw):
+    s = make_solver(inst, constraint_set=1 if boxed else 0, **kw)
+    if boxed and (lo is not None or hi is not None):
+        s.set_constraints(lo, hi)
+    return s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_box_with_equal_bounds_is_bitwise_the_equality_model(cfg1, precision):
+    need_gpu()
+    kw = dict(R=10, T=30, seed=SEED1, q_mode=1, q_fixed=12, precision=precision)
+    announce(f"box [b, b] vs equality model {precision}")
+    a = make_solver(cfg1, **kw)
+    a.run()
+    b = _solver(cfg1, lo=cfg1.b, hi=cfg1.b, **kw)
+    b.run()
+    c = _solver(cfg1, **kw)          # constraint_set = 1 without bounds: K = {b}
+    c.run()
+    la = a.log()
+    for s in (b, c):
+        lb = s.log()
+        for key in EXACT:
+            assert np.array_equal(la[key], lb[key]), key
+        assert np.all(np.isnan(lb["stop_obj"])) and np.all(np.isnan(lb["stop_feas"]))
+        ga, gb = a.get_state(), s.get_state()
+        for key in ("z", "y", "S"):
+            assert np.array_equal(ga[key].cpu().numpy(), gb[key].cpu().numpy()), key
+
+
+@pytest.mark.parametrize("trace_mode,which", [(1, "upper"), (1, "lower"), (0, "box"), (1, "box")])
+def test_general_template_trajectory_matches_oracle(cfg1, trace_mode, which):
+    need_gpu()
+    kw = dict(R=10, T=40, seed=SEED1, q_mode=1, q_fixed=8, trace_mode=trace_mode)
+    lo, hi = _boxes(cfg1, which)
+    announce(f"general template trace_mode={trace_mode} {which}")
+    s = _solver(cfg1, lo=lo, hi=hi, **kw)
+    s.run()
+    lg = s.log()
+    ref = oracle_run(cfg1, lo=lo, hi=hi, **kw)
+    assert lg["k"].tolist() == ref.log["k"].tolist()
+    assert maxrel(lg["p"], ref.log["p"]) < 1e-9
+    assert np.max(np.abs(lg["infeas"] - ref.log["infeas"]) / np.maximum(ref.log["infeas"], 1e-12)) < 1e-9
+    for key in ("xi", "gap", "gamma", "cv"):
+        assert np.max(np.abs(lg[key] - ref.log[key]) / np.maximum(np.abs(ref.log[key]), 1e-12)) < 1e-8, key
+    g = s.get_state()
+    assert maxrel(g["z"].cpu().numpy(), ref.z) < 1e-9
+    assert maxrel(g["y"].cpu().numpy(), ref.y) < 1e-9
+    assert maxrel(g["S"].cpu().numpy(), ref.S) < 1e-7
+    assert rel(g["tau"], ref.tau) < 1e-12
+    summ = s.summary()
+    assert rel(summ["objective"], ref.objective) < 1e-9
+    assert rel(summ["infeasibility"], ref.infeasibility) < 1e-9
+
+
+def test_trace_bounded_reconstruction_matches_oracle(cfg1):
+    need_gpu()
+    kw = dict(R=10, T=60, seed=SEED1, q_mode=1, q_fixed=12, trace_mode=1)
+    lo, hi = _boxes(cfg1, "upper")
+    s = _solver(cfg1, lo=lo, hi=hi, **kw)
+    s.run()
+    U, lam, err = (x.cpu().numpy() for x in s.reconstruct())
+    ref = reconstruct_result(oracle_run(cfg1, lo=lo, hi=hi, **kw))
+    tau = s.get_state()["tau"]
+    assert abs(lam.sum() - tau) < 1e-12
+    assert maxrel(lam, ref["lam"]) < 1e-8
+    assert maxrel(err, ref["err"]) < 1e-8
+    assert np.abs(U.T @ U - np.eye(10)).max() < 1e-10
+
+
+def _shifted_laplacian(inst):
+    """C = L/4 + I/4 (positive definite) on the pattern of -L/4."""
+    rows = np.repeat(np.arange(inst.n), np.diff(inst.row_ptr))
+    val = -inst.val + 0.25 * (rows == inst.col)
+    return dataclasses.replace(inst, val=val)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trace_bounded_positive_definite_objective_stays_at_zero(precision):
+    need_gpu()
+    inst = _shifted_laplacian(synth.laplacian_instance(synth.erdos_renyi(300, 1200, seed=2)))
+    s = _solver(inst, hi=np.ones(inst.n), R=4, T=30, seed=3, trace_mode=1, precision=precision)
+    s.run()
+    lg = s.log()
+    g = s.get_state()
+    assert np.all(lg["xi"] > 0)
+    assert g["p"] == 0.0 and g["tau"] == 0.0
+    assert not g["z"].any() and not g["S"].any()
+    assert np.all(lg["gap"] == 0.0) and np.all(lg["infeas"] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("which", ["upper", "lower"])
+def test_relaxed_template_reaches_the_odd_cycle_value(which, precision):
+    need_gpu()
+    inst = synth.laplacian_instance(synth.cycle(9))
+    lo, hi = _boxes(inst, which)
+    s = _solver(inst, lo=lo, hi=hi, R=4, T=3000, seed=1, trace_mode=1, precision=precision)
+    s.run()
+    ref = 4.5 * (1 + math.cos(math.pi / 9))
+    assert abs(-s.summary()["objective"] - ref) / ref < 5e-3
+
+
+def test_set_constraints_errors_and_recovery(cfg1):
+    need_gpu()
+    from paper_1912_02949_amd._lib import SCGError, SCG_EINVAL, SCG_ESTATE
+    kw = dict(R=4, T=5, seed=SEED1, q_mode=1, q_fixed=6)
+    n = cfg1.n
+    s = make_solver(cfg1, **kw)                       # constraint_set = 0
+    with pytest.raises(SCGError) as e:
+        s.set_constraints(None, np.ones(n))
+    assert e.value.status == SCG_EINVAL
+    s = make_solver(cfg1, constraint_set=1, **kw)
+    bad_lo = np.ones(n)
+    bad_lo[17] = 3.0
+    for lo, hi in ((bad_lo, np.full(n, 2.0)), (np.full(n, np.nan), None), (np.full(n, np.inf), None),
+                   (None, np.full(n, -np.inf))):
+        with pytest.raises(SCGError) as e:
+            s.set_constraints(lo, hi)
+        assert e.value.status == SCG_EINVAL
+    s.run()                                            # the rejected bounds left K = {b}
+    a = make_solver(cfg1, **kw)
+    a.run()
+    assert np.array_equal(a.log()["p"], s.log()["p"])
+    s2 = make_solver(cfg1, constraint_set=1, **kw)
+    s2.step(1)
+    with pytest.raises(SCGError) as e:
+        s2.set_constraints(None, np.ones(n))
+    assert e.value.status == SCG_ESTATE
+
+
+def test_general_template_at_full_size_fp64():
+    # the 1M-vertex torus, tr X <= alpha and diag X <= 1, two iterations of the
+    # paper's q_t schedule against the oracle
+    need_gpu()
+    inst = synth.config_instance(2)
+    kw = dict(R=10, T=2, seed=synth.CONFIG_SEEDS[2], trace_mode=1)
+    hi = np.ones(inst.n)
+    announce(f"general template full size n={inst.n}")
+    s = _solver(inst, hi=hi, **kw)
+    s.run()
+    lg = s.log()
+    ref = oracle_run(inst, hi=hi, **kw)
+    assert lg["k"].tolist() == ref.log["k"].tolist()
+    assert maxrel(lg["p"], ref.log["p"]) < 1e-8
+    assert maxrel(lg["infeas"], ref.log["infeas"]) < 1e-8
+    g = s.get_state()
+    assert maxrel(g["z"].cpu().numpy(), ref.z) < 1e-8
+    assert maxrel(g["y"].cpu().numpy(), ref.y) < 1e-8
