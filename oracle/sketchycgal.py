@@ -33,16 +33,18 @@ Readings of points the paper leaves open (the library takes the same ones):
   R10 Gap and stopping quantities at iteration t use the state before the
       update (p_t, z_t, y_t, beta_t) and xi_t in place of lambda_min(D_t), with
       the factor alpha on xi that the general trace bound alpha implies.
-  R11 General template (Appendix D, alg:full-sketchy-cgal-supp) with A = diag and
+  R11 Full reorthogonalisation is an option (approx_min_evec, reorth = 2).
+  R12 General template (Appendix D, alg:full-sketchy-cgal-supp) with A = diag and
       K a box {lo <= u <= hi}: the projection onto the box is the entrywise
       clamp (the inequality example of Appendix D.3 prints the negative part
       of w - b; the projection onto {u <= b} is b + (w - b)_- = min(w, b)).
-      The scaling divides lo and hi by alpha like b.  With H = 0 (trace-bounded
-      set, xi >= 0) the sketch takes RankOneUpdate(0, eta), so it keeps
-      following X_t+1 = (1 - eta) X_t.  The dual step rule of Appendix D.4 has
-      the same bound as eqn sketchy-cgal-dual-step.  The logged infeasibility is
-      dist_K(z_t+1), the feasibility gap of Appendix E.
-  R12 With tr X <= alpha the trace correction of the reconstruction targets the
+      The scaling divides lo and hi by alpha like b.  The dual step rule of
+      Appendix D.4 has the same bound as eqn sketchy-cgal-dual-step.
+  R13 With H = 0 (trace-bounded set, xi >= 0) the sketch takes
+      RankOneUpdate(0, eta), so it keeps following X_t+1 = (1 - eta) X_t.  The
+      logged infeasibility is dist_K(z_t+1), the feasibility gap of Appendix E;
+      the gap is <D_t, X_t - H_t>.
+  R14 With tr X <= alpha the trace correction of the reconstruction targets the
       tracked trace tau = tr X_T instead of alpha.
 """
 from __future__ import annotations
@@ -319,7 +321,7 @@ def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: n
 
     General template: given `lo` and/or `hi` (original units; a missing side is
     unbounded), the constraint is diag X in K = {u : lo <= u <= hi} and every
-    use of b in the iteration becomes a projection onto K (R11); b then only
+    use of b in the iteration becomes a projection onto K (R12); b then only
     supplies the default alpha = sum(b).  trace_mode = 1 replaces
     X in alpha*Delta_n by tr X <= alpha, whose linear minimisation returns
     H = alpha v v^T when xi < 0 and H = 0 otherwise (Appendix D.2).
@@ -418,7 +420,7 @@ def state_of(res: OracleResult, t_next: int) -> dict:
 
 def reconstruct_result(res: OracleResult, trace_correct: bool = True, storage: str = "f64"):
     """Reconstruct the final sketch of a run; U, Lambda in scaled units (X_hat = U diag(lam) U^T).
-    The trace correction targets alpha, or the tracked trace tau of X_T when tr X <= alpha (R12)."""
+    The trace correction targets alpha, or the tracked trace tau of X_T when tr X <= alpha (R14)."""
     target = res.alpha_s if res.trace_mode == 0 else res.tau
     return nystrom_reconstruct(res.S, res.Omega, res.tau, alpha=target if trace_correct else None,
                                storage=storage)
