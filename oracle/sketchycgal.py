@@ -33,7 +33,8 @@ Readings of points the paper leaves open (the library takes the same ones):
   R10 Gap and stopping quantities at iteration t use the state before the
       update (p_t, z_t, y_t, beta_t) and xi_t in place of lambda_min(D_t), with
       the factor alpha on xi that the general trace bound alpha implies.
-  R11 Full reorthogonalisation is an option (approx_min_evec, reorth = 2).
+  R11 Reorthogonalisation is an option (approx_min_evec): reorth = 1 against the
+      two most recent Lanczos vectors, reorth = 2 against all of them.
   R12 General template (Appendix D, alg:full-sketchy-cgal-supp) with A = diag and
       K a box {lo <= u <= hi}: the projection onto the box is the entrywise
       clamp (the inequality example of Appendix D.3 prints the negative part
@@ -74,7 +75,7 @@ class OracleParams:
     scale: bool = True
     trace_correct: bool = True
     instance: int = 0
-    reorth: int = 0                 # 0: none (paper); 2: full reorthogonalisation
+    reorth: int = 0                 # 0: none (paper); 1: local (last two vectors); 2: full
     trace_mode: int = 0             # 0: tr X = alpha (alpha Delta_n); 1: tr X <= alpha (Appendix D.2)
 
 
@@ -155,7 +156,9 @@ def approx_min_evec(matvec, g: np.ndarray, q: int, reorth: int = 0):
 
     reorth = 2 adds one classical Gram-Schmidt pass of the new vector against
     every stored Lanczos vector after the three-term recurrence (full
-    reorthogonalisation; not in the paper's listing, which has none).
+    reorthogonalisation; not in the paper's listing, which has none);
+    reorth = 1 makes the same pass against the two most recent ones only
+    (local reorthogonalisation, O(n) per step).
     """
     v = g / np.linalg.norm(g)
     basis = [v]
@@ -167,8 +170,8 @@ def approx_min_evec(matvec, g: np.ndarray, q: int, reorth: int = 0):
         u = matvec(v)
         om = float(np.dot(v, u))
         u = u - om * v - rho_prev * v_prev
-        if reorth == 2:
-            Vm = np.stack(basis, axis=1)
+        if reorth in (1, 2):
+            Vm = np.stack(basis if reorth == 2 else basis[-2:], axis=1)
             u = u - Vm @ (Vm.T @ u)
         r = float(np.linalg.norm(u))
         omega.append(om)
@@ -190,7 +193,7 @@ def approx_min_evec(matvec, g: np.ndarray, q: int, reorth: int = 0):
     return xi, x, {"k": k, "broke": broke, "omega": np.array(omega), "rho": np.array(rho[: k - 1])}
 
 
-def approx_min_evec_regenerated(matvec, g: np.ndarray, q: int):
+def approx_min_evec_regenerated(matvec, g: np.ndarray, q: int, reorth: int = 0):
     """Storage-optimal randomized Lanczos (alg:rand-lanczos as Section 4.2 states it).
 
     Only the two most recent Lanczos vectors are ever held.  The first sweep
@@ -198,7 +201,10 @@ def approx_min_evec_regenerated(matvec, g: np.ndarray, q: int):
     computed; the second sweep restarts the same recurrence from the same
     start vector and sums u_j v_j as the vectors come back.  Returns what
     approx_min_evec returns (reading R5: in exact arithmetic the two agree).
+    reorth = 1 (local reorthogonalisation) needs only the vectors held here.
     """
+    if reorth not in (0, 1):
+        raise ValueError("the regenerated basis supports reorth 0 or 1")
     def sweep(coef):
         v = g / np.linalg.norm(g)
         v_prev = np.zeros_like(v)
@@ -214,6 +220,9 @@ def approx_min_evec_regenerated(matvec, g: np.ndarray, q: int):
             u = matvec(v)
             om = float(np.dot(v, u))
             u = u - om * v - rho_prev * v_prev
+            if reorth == 1:
+                Vm = np.stack([v] if i == 1 else [v_prev, v], axis=1)
+                u = u - Vm @ (Vm.T @ u)
             r = float(np.linalg.norm(u))
             omega.append(om)
             if r <= 64.0 * EPS64 * (abs(om) + rho_prev):

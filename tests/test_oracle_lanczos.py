@@ -26,14 +26,16 @@ def _lanczos_coeffs(M, g, q, reorth=0):
     return xi, v, info
 
 
+@pytest.mark.parametrize("reorth", [0, 1, 2])
 @pytest.mark.parametrize("k", [2, 3, 5, 6])
-def test_tridiagonal_is_projection_on_krylov_space(k):
+def test_tridiagonal_is_projection_on_krylov_space(k, reorth):
     rng = np.random.default_rng(k)
     n = 40
     M, _ = _sym(n, rng)
     g = rng.standard_normal(n)
-    # k Lanczos steps produce omega_1..k and rho_1..k-1
-    _, _, info = _lanczos_coeffs(M, g, k)
+    # k Lanczos steps produce omega_1..k and rho_1..k-1 (any reorthogonalisation
+    # leaves them unchanged in exact arithmetic)
+    _, _, info = _lanczos_coeffs(M, g, k, reorth)
     K = np.empty((n, k))
     x = g / np.linalg.norm(g)
     for j in range(k):
@@ -48,7 +50,7 @@ def test_tridiagonal_is_projection_on_krylov_space(k):
     assert np.abs(np.triu(T, 2)).max() < 1e-10
 
 
-@pytest.mark.parametrize("reorth", [0, 2])
+@pytest.mark.parametrize("reorth", [0, 1, 2])
 def test_ritz_value_interlaces_and_converges(reorth):
     rng = np.random.default_rng(11)
     n = 120
@@ -140,3 +142,37 @@ def test_tridiagonal_solver_against_dense():
         w, V = np.linalg.eigh(T)
         assert abs(xi - w[0]) < 1e-13
         assert abs(abs(u @ V[:, 0]) - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_local_reorthogonalisation(seed):
+    # reorth = 1 keeps each new vector orthogonal to the two before it to about
+    # one ulp, where the plain recurrence (or a pass against the last vector
+    # only) drifts to 1e-15..1e-13 once the Ritz values converge; the
+    # regenerated form reproduces the stored one
+    rng = np.random.default_rng(seed)
+    n, q = 80, 60
+    M, ev = _sym(n, rng)
+    ev = ev.copy()
+    Q = np.linalg.eigh(M)[1]
+    ev[0], ev[1] = -3.0, -2.5          # a separated minimum: fast convergence
+    M = (Q * ev) @ Q.T
+    g = rng.standard_normal(n)
+
+    def local_orth(reorth):
+        B = []
+        out = approx_min_evec(lambda x: (B.append(x.copy()), M @ x)[1], g, q, reorth)
+        m1 = max(abs(B[i] @ B[i - 1]) for i in range(1, len(B)))
+        m2 = max(abs(B[i] @ B[i - 2]) for i in range(2, len(B)))
+        return out, max(m1, m2)
+
+    (xi_s, v_s, info_s), o1 = local_orth(1)
+    _, o0 = local_orth(0)
+    assert o1 < 3e-16 < 1e-15 < o0
+    xi_r, v_r, info_r = approx_min_evec_regenerated(lambda x: M @ x, g, q, 1)
+    assert xi_r == xi_s
+    np.testing.assert_array_equal(info_r["omega"], info_s["omega"])
+    np.testing.assert_allclose(v_r, v_s, rtol=0, atol=1e-14)
+    assert abs(xi_s + 3.0) < 1e-12
+    with pytest.raises(ValueError):
+        approx_min_evec_regenerated(lambda x: M @ x, g, q, 2)
