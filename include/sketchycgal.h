@@ -72,7 +72,9 @@ typedef struct {
     int32_t  q_fixed;       /* used when q_mode = 1                                          */
     int32_t  scale;         /* 1: scale the problem (Section 7.1.1); 0: solve as given       */
     int32_t  trace_correct; /* 1: trace-correct Lambda in reconstruct (alg:sketchy-cgal)     */
-    int32_t  reorth;        /* 0: Lanczos as in alg:rand-lanczos; 2: full reorthogonalisation */
+    int32_t  reorth;        /* 0: Lanczos as in alg:rand-lanczos; 1: local reorthogonalisation
+                               (one Gram-Schmidt pass against v_{i-1}, v_i); 2: full (against
+                               every stored vector).  The batched engine takes 0 or 2          */
     int32_t  precision;     /* scg_precision                                                 */
     int32_t  instance;      /* Philox counter word selecting this problem's random streams   */
     int32_t  matrix_format; /* 0: compress the off-diagonal values when they share one
@@ -90,7 +92,7 @@ typedef struct {
                                second Lanczos pass that regenerates the basis bitwise (the
                                storage-optimal randomized Lanczos of Section 4.2, alg
                                rand-lanczos; 0 is the time-storage trade-off its remark
-                               describes).  1 requires reorth = 0 (singleton engine only)     */
+                               describes).  1 requires reorth 0 or 1 (singleton engine only)  */
     int32_t  omega_mode;    /* test matrix: 0 = stored n x R (from Philox or the caller),
                                1 = regenerated from the Philox counters wherever it is used
                                (no n x R array; the caller may not pass omega).  Singleton

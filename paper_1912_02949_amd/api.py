@@ -29,7 +29,7 @@ class Params:
     q_fixed: int = 0
     scale: int = 1
     trace_correct: int = 1
-    reorth: int = 0               # 0: paper's Lanczos; 2: full reorthogonalisation
+    reorth: int = 0               # 0: paper's Lanczos; 1: local; 2: full reorthogonalisation
     precision: str = "fp64"       # "fp64" or "fp32"
     instance: int = 0
     matrix_format: int = 0        # 0: compress equal-magnitude off-diagonal values; 1: keep values

@@ -209,6 +209,23 @@ void enqueue_prep(scg_ctx* c, const IterArgs& it) {
     hipLaunchKernelGGL((k_prep<T>), dim3(c->G), dim3(kBlock), 0, c->stream, prob<T>(c), it);
 }
 
+// Lanczos step i after its product: three-term update (accumulating the Ritz
+// vector in the second sweep of a regenerated basis), then the optional
+// reorthogonalisation against v_j0 .. v_i.
+template <typename T>
+void enqueue_update(scg_ctx* c, const Prob<T>& P, int i, int accum) {
+    const dim3 g(c->G), b(kBlock);
+    if (c->prm.reorth == 0) {
+        hipLaunchKernelGGL((k_lupdate<T>), g, b, 0, c->stream, P, i, 1, accum);
+        return;
+    }
+    const int j0 = (c->prm.reorth == 2) ? 0 : std::max(0, i - 1);
+    hipLaunchKernelGGL((k_lupdate<T>), g, b, 0, c->stream, P, i, 0, accum);
+    hipLaunchKernelGGL((k_reorth_dot<T>), g, b, 0, c->stream, P, i, j0);
+    hipLaunchKernelGGL(k_reduce_h, dim3(1), b, 0, c->stream, c->sc, P.p_h, c->G, i, j0);
+    hipLaunchKernelGGL((k_reorth_apply<T>), g, b, 0, c->stream, P, i, j0);
+}
+
 template <typename T>
 void enqueue_iteration(scg_ctx* c, int t) {
     const IterArgs it = iter_args(c, t);
@@ -217,14 +234,7 @@ void enqueue_iteration(scg_ctx* c, int t) {
     for (int i = 0; i < it.q; ++i) {
         launch_spmv<T, SPMV_LANCZOS>(c, basis_col<T>(c, i), i);
         if (i == it.q - 1) break;   // rho_q and v_{q+1} are never used
-        if (c->prm.reorth == 2) {
-            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 0, 0);
-            hipLaunchKernelGGL((k_reorth_dot<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i);
-            hipLaunchKernelGGL(k_reduce_h, dim3(1), dim3(kBlock), 0, c->stream, c->sc, P.p_h, c->G, i);
-            hipLaunchKernelGGL((k_reorth_apply<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i);
-        } else {
-            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 1, 0);
-        }
+        enqueue_update<T>(c, P, i, 0);
     }
     hipLaunchKernelGGL((k_tridiag<T>), dim3(1), dim3(kBlock), 0, c->stream, P, it.q);
     if (c->prm.basis_mode == 1) {
@@ -233,7 +243,7 @@ void enqueue_iteration(scg_ctx* c, int t) {
         enqueue_prep<T>(c, it);
         for (int i = 0; i + 1 < it.q; ++i) {
             launch_spmv<T, SPMV_LANCZOS>(c, basis_col<T>(c, i), i);
-            hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, i, 1, 1);
+            enqueue_update<T>(c, P, i, 1);
         }
     }
     launch_ritz<T>(c, it.q);
@@ -704,14 +714,14 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (!(p->beta0 > 0.0) || !(p->K >= 0.0)) return false;
     if (p->q_mode != 0 && p->q_mode != 1) return false;
     if (p->q_mode == 1 && p->q_fixed < 1) return false;
-    if (p->reorth != 0 && p->reorth != 2) return false;
+    if (p->reorth < 0 || p->reorth > 2) return false;
     if (p->precision != SCG_FP64 && p->precision != SCG_FP32_STREAM) return false;
     if (qmax_for(*p, n) + 1 > kQCap) return false;
     const int l = p->spmv_lanes;
     if (l != 0 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
     if (p->spmv_grid < 0 || p->spmv_grid > kGMax) return false;
     if (p->basis_mode != 0 && p->basis_mode != 1) return false;
-    if (p->basis_mode == 1 && p->reorth != 0) return false;   // reorthogonalisation needs the stored basis
+    if (p->basis_mode == 1 && p->reorth == 2) return false;   // full reorthogonalisation needs the stored basis
     if (p->omega_mode != 0 && p->omega_mode != 1) return false;
     if (p->trace_mode != 0 && p->trace_mode != 1) return false;
     if (p->constraint_set != 0 && p->constraint_set != 1) return false;

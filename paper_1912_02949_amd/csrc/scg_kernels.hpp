@@ -459,56 +459,58 @@ __global__ __launch_bounds__(kBlock) void k_lupdate(Prob<T> P, int step, int wit
     }
 }
 
-// Full reorthogonalisation, part 1: per-workgroup partials of v_j^T w, j <= step.
+// Reorthogonalisation, part 1: per-workgroup partials of v_j^T w, j = j0 .. step.
+// j0 = 0 for the full pass, step - 1 (or 0) for the local one, which only needs
+// the vectors a regenerated basis keeps.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_reorth_dot(Prob<T> P, int step) {
+__global__ __launch_bounds__(kBlock) void k_reorth_dot(Prob<T> P, int step, int j0) {
     DevScalars* sc = P.sc;
     if (sc->done) return;
     const int64_t n = P.n;
-    const int nj = step + 1;
-    const T* w = P.V + (size_t)(step + 1) * P.ld;
+    const int nj = step + 1 - j0;
+    const T* w = vcol(P, step + 1);
     int64_t lo, hi;
     split_range(n, xcd_lid(), gridDim.x, lo, hi);
     __shared__ double red[kWaves];
-    for (int j = 0; j < nj; ++j) {
-        const T* vj = P.V + (size_t)j * P.ld;
+    for (int jj = 0; jj < nj; ++jj) {
+        const T* vj = vcol(P, j0 + jj);
         double acc = 0.0;
         for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) acc += (double)vj[r] * (double)w[r];
         const double bs = block_sum(acc, red);
-        if (threadIdx.x == 0) P.p_h[(size_t)blockIdx.x * nj + j] = bs;
+        if (threadIdx.x == 0) P.p_h[(size_t)blockIdx.x * nj + jj] = bs;
     }
 }
 
-// Part 2 (one workgroup): h_j = inv_j * sum of the partials.
-__global__ __launch_bounds__(kBlock) void k_reduce_h(DevScalars* sc, const double* p_h, int G, int step) {
+// Part 2 (one workgroup): h_j = inv_j * sum of the partials, j = j0 .. step.
+__global__ __launch_bounds__(kBlock) void k_reduce_h(DevScalars* sc, const double* p_h, int G, int step, int j0) {
     if (sc->done) return;
     __shared__ double red[kWaves];
-    const int nj = step + 1;
-    for (int j = 0; j < nj; ++j) {
+    const int nj = step + 1 - j0;
+    for (int jj = 0; jj < nj; ++jj) {
         double s = 0.0;
-        for (int g = threadIdx.x; g < G; g += kBlock) s += p_h[(size_t)g * nj + j];
+        for (int g = threadIdx.x; g < G; g += kBlock) s += p_h[(size_t)g * nj + jj];
         s = block_sum(s, red);
-        if (threadIdx.x == 0) sc->h[j] = s * sc->inv[j];
+        if (threadIdx.x == 0) sc->h[j0 + jj] = s * sc->inv[j0 + jj];
     }
 }
 
-// Part 3: w <- w - sum_j h_j v_hat_j; partial sums of ||w||^2.
+// Part 3: w <- w - sum_j h_j v_hat_j (j = j0 .. step); partial sums of ||w||^2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_reorth_apply(Prob<T> P, int step) {
+__global__ __launch_bounds__(kBlock) void k_reorth_apply(Prob<T> P, int step, int j0) {
     DevScalars* sc = P.sc;
     if (sc->done) return;
     __shared__ double hc[kQCap];
-    const int nj = step + 1;
-    for (int j = threadIdx.x; j < nj; j += kBlock) hc[j] = sc->h[j] * sc->inv[j];
+    const int nj = step + 1 - j0;
+    for (int jj = threadIdx.x; jj < nj; jj += kBlock) hc[jj] = sc->h[j0 + jj] * sc->inv[j0 + jj];
     __syncthreads();
     const int64_t n = P.n;
-    T* w = P.V + (size_t)(step + 1) * P.ld;
+    T* w = vcol(P, step + 1);
     int64_t lo, hi;
     split_range(n, xcd_lid(), gridDim.x, lo, hi);
     double acc = 0.0;
     for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
         double a = 0.0;
-        for (int j = 0; j < nj; ++j) a += hc[j] * (double)P.V[(size_t)j * P.ld + r];
+        for (int jj = 0; jj < nj; ++jj) a += hc[jj] * (double)vcol(P, j0 + jj)[r];
         const T wt = (T)((double)w[r] - a);
         w[r] = wt;
         acc += (double)wt * (double)wt;

@@ -54,7 +54,7 @@ def test_workspace_size_and_validation():
     st2, b2 = _ws(precision=_lib.SCG_FP32_STREAM)
     assert st2 == _lib.SCG_OK and b2 < b
     bad = [dict(R=0), dict(R=33), dict(n=5, R=6), dict(T=0), dict(beta0=0.0), dict(beta0=-1.0), dict(K=-1.0),
-           dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=1), dict(precision=7), dict(n=0),
+           dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=3), dict(reorth=-1), dict(precision=7), dict(n=0),
            dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_grid=-1), dict(spmv_grid=4096),
            dict(q_mode=1, q_fixed=600, n=10_000), dict(basis_mode=2), dict(basis_mode=-1), dict(omega_mode=2),
            dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=2)]

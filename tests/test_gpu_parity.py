@@ -103,7 +103,7 @@ def test_first_lanczos_run_matches(cfg1):
     assert rel(xi, xi_o) < 1e-12
 
 
-@pytest.mark.parametrize("reorth,q", [(2, 36), (0, 8)])
+@pytest.mark.parametrize("reorth,q", [(2, 36), (0, 8), (1, 8)])
 def test_single_iteration_from_oracle_state_fp64(cfg1, reorth, q):
     need_gpu()
     kw = dict(R=10, T=500, seed=SEED1, q_mode=1, q_fixed=q, reorth=reorth)
@@ -138,9 +138,10 @@ def test_single_iteration_from_oracle_state_fp64(cfg1, reorth, q):
         assert rel(lg["cv"][t - 1], ref.log["cv"][-1]) < 1e-9, t
 
 
-def test_trajectory_small_q_fp64(cfg1):
+@pytest.mark.parametrize("reorth", [0, 1])
+def test_trajectory_small_q_fp64(cfg1, reorth):
     need_gpu()
-    kw = dict(R=10, T=40, seed=SEED1, q_mode=1, q_fixed=8)
+    kw = dict(R=10, T=40, seed=SEED1, q_mode=1, q_fixed=8, reorth=reorth)
     s = make_solver(cfg1, **kw)
     s.run()
     lg = s.log()
