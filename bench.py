@@ -146,6 +146,16 @@ class Solve:
         self.lib.sketchycgal_summary(self.ctx, C.byref(s))
         return {k: getattr(s, k) for k, _ in _lib.scg_summary._fields_}
 
+    def last_record(self):
+        """The last iteration's log record (scaled units), as a dict."""
+        from paper_1912_02949_amd import _lib
+        cap = self.prm.T
+        arr = (_lib.scg_iter_log * cap)()
+        cnt = C.c_int32()
+        _lib.check(self.lib.sketchycgal_log(self.ctx, arr, cap, C.byref(cnt)), "log")
+        rec = arr[cnt.value - 1]
+        return {k: getattr(rec, k) for k, _ in _lib.scg_iter_log._fields_}
+
     def infeasibility_log(self):
         """||diag X_{t+1} - b|| per iteration, original units."""
         from paper_1912_02949_amd import _lib
@@ -361,6 +371,8 @@ def main():
     progress(f"fp32 solves: {1e3 * dt32 / args.steps:.1f} ms each")
     sum32 = s32.summary()
     infeas32 = s32.infeasibility_log()
+    last32 = s32.last_record()
+    norm_b = math.sqrt(float((inst.b * inst.b).sum()))
     cut_w, cut_j, cut_s = s32.round_cut()
     # SpMV kernel leg: back-to-back launches on the solver's stream, HIP events
     ms = C.c_double()
@@ -386,12 +398,15 @@ def main():
         dt64 = timed(s64, args.steps, args.warmup, torch)
         progress(f"fp64 solves: {1e3 * dt64 / args.steps:.1f} ms each")
         sum64 = s64.summary()
+        last64 = s64.last_record()
         s64.close()
         fp64 = {
             "value": args.steps * T / dt64,
             "ms_per_step": 1e3 * dt64 / args.steps,
             "objective": sum64["objective"],
             "infeasibility": sum64["infeasibility"],
+            "infeasibility_rel": sum64["infeasibility"] / norm_b,
+            "eigen_residual_scaled": last64["resid"],
         }
         # speedup at equal final infeasibility: the FP32 solve stopped at the first iteration whose
         # ||diag X - b|| is at most the FP64 solve's final value, timed as a whole solve
@@ -482,6 +497,10 @@ def main():
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "result_fp32": {"objective": sum32["objective"], "infeasibility": sum32["infeasibility"],
+                        "infeasibility_rel": sum32["infeasibility"] / norm_b,
+                        "eigen_residual_scaled": last32["resid"], "xi_scaled": last32["xi"],
+                        "objective_rel_diff_vs_fp64": (abs(sum32["objective"] - fp64["objective"]) /
+                                                       abs(fp64["objective"])) if fp64 else None,
                         "rounded_cut_weight": cut_w, "rounded_cut_column": cut_j, "rounding_ms": 1e3 * cut_s,
                         "cut_over_sdp_objective": cut_w / -sum32["objective"]},
         "storage_optimal_fp32": storage,
