@@ -283,6 +283,15 @@ scg_status sketchycgal_batch_init(scg_batch** out, const scg_params* p, int32_t 
  * past T. */
 scg_status sketchycgal_batch_step(scg_batch* ctx, int32_t iters);
 
+/* Per-problem initial penalty: problem k runs with beta_t = beta0[k] sqrt(t + 1)
+ * and the dual step bound of eqn sketchy-cgal-dual-step with beta0[k]
+ * (alg:sketchy-cgal; every problem keeps its own iteration counter).
+ *   beta0  host double[n_inst], each > 0 and finite (SCG_EINVAL otherwise);
+ *          copied.  Until it is called every problem takes params.beta0.
+ * Must come before the first sketchycgal_batch_step or set_state
+ * (SCG_ESTATE otherwise).  Synchronises the stream. */
+scg_status sketchycgal_batch_set_beta0(scg_batch* ctx, const double* beta0);
+
 /* Per-problem iteration records, summary (original units), checkpoint state
  * (z, y device double[n_i]; S device double[n_i*R] row-major; any pointer of
  * get_state may be NULL; set_state puts problem `inst` at iteration t_next,

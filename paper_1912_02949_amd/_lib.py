@@ -48,7 +48,7 @@ EXPORTS = [
     "sketchycgal_destroy", "scg_status_string", "sketchycgal_round", "sketchycgal_set_constraints",
     "scg_batch_workspace_size", "sketchycgal_batch_init", "sketchycgal_batch_step", "sketchycgal_batch_log",
     "sketchycgal_batch_summary", "sketchycgal_batch_get_state", "sketchycgal_batch_set_state", "sketchycgal_batch_reconstruct",
-    "sketchycgal_batch_destroy", "sketchycgal_batch_round",
+    "sketchycgal_batch_destroy", "sketchycgal_batch_round", "sketchycgal_batch_set_beta0",
 ]
 
 _lib = None
@@ -83,6 +83,7 @@ def load() -> C.CDLL:
     lib.scg_batch_workspace_size.argtypes = [P(scg_params), i32, vp, i64, P(sz)]
     lib.sketchycgal_batch_init.argtypes = [P(vp), P(scg_params), i32, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     lib.sketchycgal_batch_step.argtypes = [vp, i32]
+    lib.sketchycgal_batch_set_beta0.argtypes = [vp, vp]
     lib.sketchycgal_batch_log.argtypes = [vp, i32, P(scg_iter_log), i32, P(i32)]
     lib.sketchycgal_batch_summary.argtypes = [vp, i32, P(scg_summary)]
     lib.sketchycgal_batch_get_state.argtypes = [vp, i32, P(i32), vp, vp, vp, P(C.c_double), P(C.c_double)]

@@ -256,6 +256,13 @@ class BatchedSketchyCGAL:
             self.lib.sketchycgal_batch_destroy(ctx)
             self.ctx = None
 
+    def set_beta0(self, beta0):
+        """Per-problem initial penalty beta_0 (before the first step)."""
+        arr = np.ascontiguousarray(np.asarray(beta0, dtype=np.float64))
+        if arr.shape != (len(self.inst_n),):
+            raise ValueError("one beta0 per problem")
+        check(self.lib.sketchycgal_batch_set_beta0(self.ctx, arr.ctypes.data), "sketchycgal_batch_set_beta0")
+
     def step(self, iters: int = 1):
         check(self.lib.sketchycgal_batch_step(self.ctx, iters), "sketchycgal_batch_step")
 

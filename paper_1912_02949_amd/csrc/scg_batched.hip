@@ -64,6 +64,7 @@ struct BatchInst {
     double cval;       // common off-diagonal value / magnitude, scaled (compressed formats)
     double alpha_s;    // alpha in scaled units
     double c_F, alpha; // scaling constants
+    double beta0;      // the instance's initial penalty beta_0 (its schedule beta_t = beta_0 sqrt(t + 1))
 };
 
 struct BatchScal {
@@ -318,7 +319,7 @@ __device__ __forceinline__ void iteration_tail(const BatchArgs<T, CT>& A, const 
         breduce<3>(pa, red, so + SO_PRIM);
     }
     const double r2 = so[SO_PRIM];
-    double gamma = (r2 == 0.0) ? A.beta0 : fmin(A.beta0, 4.0 * alpha * alpha * A.beta0 / (pow(t + 1.0, 1.5) * r2));
+    double gamma = (r2 == 0.0) ? D.beta0 : fmin(D.beta0, 4.0 * alpha * alpha * D.beta0 / (pow(t + 1.0, 1.5) * r2));
     if (guard) {
         const double ny2 = so[SO_PRIM + 1] + 2.0 * gamma * so[SO_PRIM + 2] + gamma * gamma * r2;
         if (sqrt(fmax(ny2, 0.0)) > A.K) gamma = 0.0;
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
     const int64_t ld = D.ld;
     const int tid = threadIdx.x;
     const int q = A.qtab[(size_t)ii * A.T_iters + (t - 1)];
-    const double beta = A.beta0 * sqrt(t + 1.0);
+    const double beta = D.beta0 * sqrt(t + 1.0);
     const double eta = 2.0 / (t + 1.0);
     const double cv = (FMT == FMT_VAL) ? 1.0 : D.cval;
     const int32_t* rp = A.rp + D.row0;
@@ -675,7 +676,7 @@ __global__ __launch_bounds__(kBT) void k_batch_iter(BatchArgs<T, CT> A) {
     const int64_t ld = D.ld;
     const int tid = threadIdx.x;
     const int q = A.qtab[(size_t)ii * A.T_iters + (t - 1)];
-    const double beta = A.beta0 * sqrt(t + 1.0);
+    const double beta = D.beta0 * sqrt(t + 1.0);
     const double eta = 2.0 / (t + 1.0);
     const double cv = (FMT == FMT_VAL) ? 1.0 : D.cval;
     const int32_t* rp = A.rp + D.row0;
@@ -1455,6 +1456,7 @@ scg_status sketchycgal_batch_init(scg_batch** out, const scg_params* p, int32_t 
         I.pos0 = pv;
         I.n = (int)n;
         I.id = p->instance + k;
+        I.beta0 = p->beta0;
         I.ld = (n + 63) / 64 * 64;
         int qm = 1;
         for (int t = 1; t <= p->T; ++t) qm = std::max(qm, q_of(*p, n, t));
@@ -1485,6 +1487,18 @@ scg_status sketchycgal_batch_init(scg_batch** out, const scg_params* p, int32_t 
 // One launch per iteration; on a non-null stream, runs of kGraphChunk iterations
 // replay one captured graph (the launches are identical: each instance's
 // iteration counter lives on the device).
+scg_status sketchycgal_batch_set_beta0(scg_batch* c, const double* beta0) {
+    if (!c || !beta0) return SCG_EINVAL;
+    for (int k = 0; k < c->ninst; ++k)
+        if (!(beta0[k] > 0.0) || !std::isfinite(beta0[k])) return SCG_EINVAL;
+    for (int k = 0; k < c->ninst; ++k)
+        if (c->t_host[k] != 1) return SCG_ESTATE;
+    for (int k = 0; k < c->ninst; ++k) c->hinst[k].beta0 = beta0[k];
+    HIP_TRY(hipMemcpyAsync(c->inst, c->hinst.data(), sizeof(BatchInst) * c->ninst, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCG_OK;
+}
+
 scg_status sketchycgal_batch_step(scg_batch* c, int32_t iters) {
     if (!c || iters < 0) return SCG_EINVAL;
     const int tmax = *std::max_element(c->t_host.begin(), c->t_host.end());

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:scg|sketchycgal)_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b((?:scg|sketchycgal)_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported():
@@ -157,3 +157,4 @@ def test_batch_init_rejects_null_and_misaligned_arguments():
                                       1 << 30, None) == _lib.SCG_EINVAL
     assert ctx.value is None
     assert lib.sketchycgal_batch_step(None, 1) == _lib.SCG_EINVAL
+    assert lib.sketchycgal_batch_set_beta0(None, None) == _lib.SCG_EINVAL

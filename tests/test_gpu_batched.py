@@ -69,6 +69,42 @@ def test_batched_trajectories_match_oracle_fp64(kind, fmt):
         assert maxrel(g["z"].cpu().numpy(), ref.z) < Z_TOL, i
 
 
+def test_batched_per_instance_beta0_matches_oracle_fp64():
+    # Each problem with its own beta_0 (0.5 .. 4) against the oracle run with it.
+    # Oracle floors of these seven runs, measured by a 1-ulp start-vector change
+    # and by summing every row in reverse order: p <= 3.4e-9, ||z - b|| <= 1.9e-8,
+    # z <= 2.8e-7 (the n = 1205 member at beta_0 = 2); bars at 20x those.
+    tol, ztol = 4e-7, 6e-6
+    need_gpu()
+    insts = traj_batch()
+    betas = [0.5, 2.0, 1.0, 4.0]
+    kw = dict(R=8, T=40, seed=SEED4, q_mode=1, q_fixed=8)
+    bt = make_batch(insts, **kw)
+    b0 = np.array([betas[i % len(betas)] for i in range(len(insts))])
+    bt.set_beta0(b0)
+    bt.run()
+    for i, inst in enumerate(insts):
+        ref = oracle_run(inst, instance=i, beta0=float(b0[i]), **kw)
+        _check_trajectory(bt.log(i), ref, tol, ("beta0", i))
+        assert maxrel(bt.get_state(i)["z"].cpu().numpy(), ref.z) < ztol, i
+        assert np.allclose(bt.log(i)["beta"], b0[i] * np.sqrt(np.arange(2, 42))), i
+
+
+def test_batched_set_beta0_errors():
+    need_gpu()
+    from paper_1912_02949_amd._lib import SCGError, SCG_EINVAL, SCG_ESTATE
+    insts = traj_batch()[:3]
+    bt = make_batch(insts, R=8, T=5, seed=SEED4, q_mode=1, q_fixed=6)
+    for bad in ([1.0, 0.0, 1.0], [1.0, -2.0, 1.0], [1.0, np.nan, 1.0], [np.inf, 1.0, 1.0]):
+        with pytest.raises(SCGError) as e:
+            bt.set_beta0(bad)
+        assert e.value.status == SCG_EINVAL
+    bt.step(1)
+    with pytest.raises(SCGError) as e:
+        bt.set_beta0([1.0, 1.0, 1.0])
+    assert e.value.status == SCG_ESTATE
+
+
 @pytest.mark.parametrize("which", ["unit", "weighted"])
 def test_batched_single_iteration_from_oracle_state_fp64(which):
     need_gpu()
