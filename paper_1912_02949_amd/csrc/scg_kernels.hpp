@@ -1,22 +1,25 @@
 // Kernels of one SketchyCGAL iteration (alg:sketchy-cgal) on gfx950.
 //
 // Per iteration t the host enqueues, with no synchronisation:
-//   k_prep        shift s = dC + y + beta (z - b) (primitive 2), Lanczos start
-//                 vector (Philox normals), and the pre-update dot products
-//                 for the gap / stopping quantities
+//   k_prep        shift s = dC + y + beta (z - w) (primitive 2; w = b, or the
+//                 slack proj_K(z + y / beta) of a box constraint set), Lanczos
+//                 start vector (Philox normals), and the pre-update dot
+//                 products for the gap / stopping quantities
 //   q_t x { k_spmv<LANCZOS>   u = D v_i (primitives 1+2), omega_i = v_i^T u
 //           k_lupdate         v_{i+1} = u - omega_i v_i - rho_{i-1} v_{i-1},
 //                             rho_i = ||v_{i+1}||  (three-term recurrence)
-//           [k_reorth_dot, k_reduce_h, k_reorth_apply: full reorthogonalisation] }
+//           [k_reorth_dot, k_reduce_h, k_reorth_apply: reorthogonalisation
+//            against v_0 .. v_i (full) or v_{i-1}, v_i (local)] }
 //   k_tridiag     (xi, u) = MinEvec(T_k) in FP64, Ritz coefficients
 //   k_ritz        v = sum_j u_j v_j, ||v||, v^T Omega
 //                 (regenerated basis: k_prep and q_t - 1 x {k_spmv, k_lupdate} run
 //                 again, identically, with k_lupdate adding u_j v_j into an FP64
 //                 accumulator, and k_ritz_regen adds the last term)
 //   k_spmv<OBJ>   v^T C v (objective tracker), ||D v - xi v||
-//   k_primal      z <- (1-eta) z + eta alpha v.v (primitive 3), ||z - b||
-//   k_dual_sketch dual step size, y <- y + gamma (z - b),
-//                 S <- (1-eta) S + eta alpha v (v^T Omega), p, tau, log record
+//   k_primal      z <- (1-eta) z + eta ha v.v (primitive 3; ha = alpha, or 0 when
+//                 tr X <= alpha and xi >= 0), ||z - w_bar||, dist_K(z)
+//   k_dual_sketch dual step size, y <- y + gamma (z - w_bar),
+//                 S <- (1-eta) S + eta ha v (v^T Omega), p, tau, log record
 //
 // Reductions: each kernel stores one partial sum per workgroup; the next
 // kernel adds them in workgroup order at its start (reduce_partials).  All
