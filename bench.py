@@ -275,6 +275,19 @@ def spmv_line(torch, k: int, precision: str):
             "matrix_format": ["values", "columns only", "columns with sign bit"][summ["matrix_format"]]}
 
 
+def batched_bytes(n: int, m: int, k: int, es: int, cb: int, vb: int, R: int) -> int:
+    """Bytes one batched iteration of a problem with n rows, m off-diagonal entries and k Lanczos steps
+    streams through memory, each array counted once per pass as the kernel reads or writes it:
+    prep (z, y, b, diag C read; shift and start vector written), the shift in slice order (permutation,
+    shift gathered and written), k products (permutation, shift, product written; column words and
+    values), k - 1 three-term updates (product and v_{i-1} read, v_{i+1} written), the Ritz combination
+    (k basis vectors), the norm and v^T Omega (Omega), the objective product (permutation, shift,
+    diagonal; column words and values) and the tail (z, y read and written, b twice, S read and written)."""
+    per_row = (32 + 2 * es) + (4 + 2 * es) + k * (4 + 2 * es) + (k - 1) * 3 * es + k * es + R * es \
+        + (12 + es) + (56 + 2 * es * R)
+    return n * per_row + (k + 1) * (cb + vb) * m
+
+
 def batched_leg(torch, T: int, with_fp64: bool):
     """Whole batched solves (init excluded from the rate, reported beside it)."""
     import synth
@@ -293,10 +306,23 @@ def batched_leg(torch, T: int, with_fp64: bool):
         b.synchronize()
         t2 = time.perf_counter()
         infeas = [b.summary(i)["infeasibility"] / math.sqrt(insts[i].n) for i in range(len(insts))]
+        # algorithmic bytes of the whole run from every problem's recorded Lanczos steps (the sliced
+        # kernel, which keeps the multiplied vector in LDS: FP32 on this workload; FP64 vectors of the
+        # largest problems exceed the LDS budget and gather from global memory instead)
+        total = gbs = None
+        if prec == "fp32":
+            fmt = b.summary(0)["matrix_format"]
+            nmax = max(g.n for g in insts)
+            cb = 2 if nmax <= (32767 if fmt == 2 else 65535) else 4
+            total = sum(batched_bytes(g.n, g.nnz - g.n, int(kk), 4, cb, 0 if fmt != 0 else 4, 8)
+                        for i, g in enumerate(insts) for kk in b.log(i)["k"])
+            gbs = total / (t2 - t1) / 1e9
         out[prec] = {"batch_iters_per_s": T / (t2 - t1), "instance_iters_per_s": len(insts) * T / (t2 - t1),
                      "ms_per_iteration": 1e3 * (t2 - t1) / T, "init_s": t1 - t0,
                      "max_rel_infeasibility": max(infeas),
-                     "objective_sum": sum(b.summary(i)["objective"] for i in range(len(insts)))}
+                     "objective_sum": sum(b.summary(i)["objective"] for i in range(len(insts))),
+                     "algorithmic_bytes_per_iteration": None if total is None else total / T,
+                     "algorithmic_GBps": gbs, "frac_of_hbm_peak": None if gbs is None else gbs / HBM_PEAK_GBS}
         del b
         progress(f"batched {prec}: {out[prec]['ms_per_iteration']:.3f} ms per iteration")
     if with_fp64:
