@@ -39,8 +39,10 @@ Readings of points the paper leaves open (the library takes the same ones):
       K a box {lo <= u <= hi}: the projection onto the box is the entrywise
       clamp (the inequality example of Appendix D.3 prints the negative part
       of w - b; the projection onto {u <= b} is b + (w - b)_- = min(w, b)).
-      The scaling divides lo and hi by alpha like b.  The dual step rule of
-      Appendix D.4 has the same bound as eqn sketchy-cgal-dual-step.
+      The scaling divides lo and hi by alpha like b.  The norm-constraint
+      example of the same appendix is taken with the l2 norm, centred at b:
+      proj(w) = b + (w - b) min(1, r / ||w - b||), r scaled like b.  The dual
+      step rule of Appendix D.4 has the same bound as eqn sketchy-cgal-dual-step.
   R13 With H = 0 (trace-bounded set, xi >= 0) the sketch takes
       RankOneUpdate(0, eta), so it keeps following X_t+1 = (1 - eta) X_t.  The
       logged infeasibility is dist_K(z_t+1), the feasibility gap of Appendix E;
@@ -324,14 +326,16 @@ _LOG_KEYS = ("t", "q", "k", "xi", "cv", "p", "infeas", "gamma", "gap", "stop_obj
 def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: np.ndarray | None = None,
                  record_v: bool = False, start_vectors=None, state0: dict | None = None,
                  t_stop: int | None = None, lo: np.ndarray | None = None,
-                 hi: np.ndarray | None = None) -> OracleResult:
+                 hi: np.ndarray | None = None, radius: float | None = None) -> OracleResult:
     """SketchyCGAL (alg:sketchy-cgal) for min <C,X> s.t. diag X = b, X in alpha*Delta_n,
     and its general template (Appendix D, alg:full-sketchy-cgal-supp) with A = diag.
 
     General template: given `lo` and/or `hi` (original units; a missing side is
     unbounded), the constraint is diag X in K = {u : lo <= u <= hi} and every
     use of b in the iteration becomes a projection onto K (R12); b then only
-    supplies the default alpha = sum(b).  trace_mode = 1 replaces
+    supplies the default alpha = sum(b).  Given `radius` instead, K is the
+    ball {u : ||u - b|| <= radius} (the norm-constraint example of Appendix
+    D.3, l2 norm), centred at b.  trace_mode = 1 replaces
     X in alpha*Delta_n by tr X <= alpha, whose linear minimisation returns
     H = alpha v v^T when xi < 0 and H = 0 otherwise (Appendix D.2).
 
@@ -348,7 +352,18 @@ def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: n
     alpha0 = float(b.sum()) if params.alpha is None else float(params.alpha)
     Cs, bs, alpha, c_F = scale_problem(C, b, alpha0, params.scale)
     box = lo is not None or hi is not None
-    if box:
+    ball = radius is not None
+    if box and ball:
+        raise ValueError("K is a box or a ball, not both")
+    if ball:
+        rad_s = float(radius) / (alpha0 if params.scale else 1.0)
+
+        def proj(u):   # Euclidean projection onto the ball K (Appendix D.3): b + (u - b) min(1, r / ||u - b||)
+            d = u - bs
+            nd = float(np.linalg.norm(d))
+            c = 1.0 if nd <= rad_s else rad_s / nd
+            return bs + c * d
+    elif box:
         sK = alpha0 if params.scale else 1.0    # the scaling divides the constraint values by alpha
         lo_s = np.full(n, -np.inf) if lo is None else np.asarray(lo, dtype=np.float64) / sK
         hi_s = np.full(n, np.inf) if hi is None else np.asarray(hi, dtype=np.float64) / sK
@@ -391,7 +406,7 @@ def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: n
         ha = alpha if (params.trace_mode == 0 or xi < 0.0) else 0.0
         # surrogate gap <D_t, X_t - H_t> with <D_t, X_t> = p_t + <w, z_t> and <D_t, H_t> = ha xi
         gap = p + float(np.dot(w, z)) - ha * xi
-        if not box and params.trace_mode == 0:
+        if not (box or ball) and params.trace_mode == 0:
             zb = z - bs
             stop_obj = (p + float(np.dot(y, bs)) + 0.5 * beta * float(np.dot(zb, z + bs)) - alpha * xi) / (1.0 + abs(p))
             stop_feas = float(np.linalg.norm(zb)) / (1.0 + nb)
@@ -402,7 +417,7 @@ def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: n
         z = (1.0 - eta) * z + eta * ha * (v * v)
         zb = z - proj(z + y / (beta0 * math.sqrt(t + 2.0)))   # z - w_bar
         r2 = float(np.dot(zb, zb))
-        infeas = math.sqrt(r2) if not box else float(np.linalg.norm(z - proj(z)))
+        infeas = math.sqrt(r2) if not (box or ball) else float(np.linalg.norm(z - proj(z)))
         gamma = dual_step_size(r2, t, alpha, beta0)
         y_new = y + gamma * zb
         if np.linalg.norm(y_new) > params.K:
@@ -419,7 +434,7 @@ def sketchy_cgal(C: sp.csr_matrix, b: np.ndarray, params: OracleParams, Omega: n
     log = {k: np.array(v) for k, v in log.items()}
     return OracleResult(n=n, alpha=alpha0, c_F=c_F, alpha_s=alpha, b_s=bs, p=p, z=z, y=y, S=sketch.S,
                         tau=sketch.tau, Omega=sketch.Omega, log=log, vs=vs, trace_mode=params.trace_mode,
-                        dist_K=float(np.linalg.norm(z - proj(z))) if box else None)
+                        dist_K=float(np.linalg.norm(z - proj(z))) if (box or ball) else None)
 
 
 def state_of(res: OracleResult, t_next: int) -> dict:

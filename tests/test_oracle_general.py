@@ -11,6 +11,9 @@ tr X <= alpha.
   (n/2)(1 + cos(pi/n)).
 * The surrogate gap <D_t, X_t - H_t> is nonnegative when the eigenvector is exact
   (H_t minimises <D_t, .> over the trace set, which holds X_t).
+* The l2 ball {||diag X - b|| <= r}: radius 0 runs the equality model bit for
+  bit, the reported distance equals the closed form max(0, ||z - b|| - r), and
+  a larger ball does not lower the cut value (a larger feasible set).
 """
 import math
 
@@ -23,9 +26,9 @@ from oracle import OracleParams, sketchy_cgal
 from oracle.sketchycgal import reconstruct_result
 
 
-def _run(inst, lo=None, hi=None, C=None, **kw):
+def _run(inst, lo=None, hi=None, C=None, radius=None, **kw):
     prm = OracleParams(**kw)
-    return sketchy_cgal(inst.to_scipy() if C is None else C, inst.b, prm, lo=lo, hi=hi)
+    return sketchy_cgal(inst.to_scipy() if C is None else C, inst.b, prm, lo=lo, hi=hi, radius=radius)
 
 
 def test_box_with_equal_bounds_runs_the_equality_model():
@@ -87,3 +90,37 @@ def test_trace_bounded_reconstruction_targets_the_tracked_trace():
     rec = reconstruct_result(res)
     assert abs(rec["lam"].sum() - res.tau) < 1e-12
     assert res.tau <= res.alpha_s + 1e-12
+
+
+def test_ball_of_radius_zero_runs_the_equality_model():
+    inst = synth.laplacian_instance(synth.erdos_renyi(60, 200, seed=4))
+    kw = dict(R=5, T=40, seed=7, q_mode=1, q_fixed=10)
+    a = _run(inst, **kw)
+    b = _run(inst, radius=0.0, **kw)
+    for key in ("p", "xi", "cv", "gamma", "gap", "k"):
+        np.testing.assert_array_equal(a.log[key], b.log[key], err_msg=key)
+    np.testing.assert_array_equal(a.z, b.z)
+    np.testing.assert_array_equal(a.y, b.y)
+
+
+def test_ball_distance_and_growing_radius():
+    # dist_K(z) of a ball is max(0, ||z - b|| - r) (closed form, checked on the
+    # final state); a larger ball only lowers the optimum of the minimisation
+    inst = synth.laplacian_instance(synth.cycle(9))
+    ref = 4.5 * (1 + math.cos(math.pi / 9))
+    vals = []
+    for r in (0.0, 0.5, 1.5):
+        res = _run(inst, radius=r, R=4, T=3000, seed=1, trace_mode=1)
+        d_closed = max(0.0, float(np.linalg.norm(res.z - res.b_s)) - r / res.alpha)
+        assert abs(res.dist_K - d_closed) < 1e-15
+        vals.append(-res.objective)
+    assert abs(vals[0] - ref) / ref < 5e-3
+    assert vals[0] <= vals[1] * (1 + 2e-3) and vals[1] <= vals[2] * (1 + 2e-3)
+
+
+def test_ball_surrogate_gap_is_nonnegative_with_exact_eigenvectors():
+    g = synth.erdos_renyi(30, 90, seed=9)
+    inst = synth.laplacian_instance(g)
+    for tm in (0, 1):
+        res = _run(inst, radius=2.0, R=4, T=60, seed=2, q_mode=1, q_fixed=inst.n - 1, trace_mode=tm, reorth=2)
+        assert np.all(res.log["gap"] >= -1e-10 * (1.0 + np.abs(res.log["p"]))), tm
