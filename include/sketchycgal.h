@@ -104,8 +104,10 @@ typedef struct {
     int32_t  constraint_set;/* 0: diag X = b; 1: lo <= diag X <= hi (Appendix D.3; every use
                                of b in the iteration becomes the projection onto the box),
                                bounds from sketchycgal_set_constraints (until then lo = hi =
-                               b).  b then only gives the default alpha = sum(b).  Singleton
-                               engine only                                                    */
+                               b), b then only gives the default alpha = sum(b); 2: the l2
+                               ball ||diag X - b|| <= r (the norm-constraint example of
+                               Appendix D.3), r from sketchycgal_set_ball (until then 0).
+                               Singleton engine only                                          */
 } scg_params;
 
 /* One record per iteration t, in scaled units (see file comment).  Gap and
@@ -116,7 +118,7 @@ typedef struct {
     double xi;                /* Ritz value (approximate lambda_min(D_t))                          */
     double cv;                /* v^T C v                                                           */
     double p;                 /* p_{t+1} = <C, X_{t+1}>                                            */
-    double infeas;            /* ||z_{t+1} - b||; box constraints: dist_K(z_{t+1})                 */
+    double infeas;            /* ||z_{t+1} - b||; box or ball constraints: dist_K(z_{t+1})         */
     double gamma;             /* dual step taken (0 when the K guard refused it)                   */
     double gap;               /* surrogate duality gap g_t = <D_t, X_t - H_t>                      */
     double stop_obj;          /* relative-gap stopping quantity (NaN unless diag X = b, tr X = a)  */
@@ -131,7 +133,7 @@ typedef struct {
     int32_t t_done;           /* iterations completed                       */
     int32_t status_flags;     /* bit0: NaN/Inf seen                         */
     double objective;         /* <C, X>                                     */
-    double infeasibility;     /* ||diag X - b|| (box constraints: dist_K)   */
+    double infeasibility;     /* ||diag X - b|| (box or ball: dist_K)       */
     double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
     int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction               */
     int32_t spmv_segments;    /* column segments of the SpMV                                   */
@@ -179,6 +181,13 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
  * SCG_EINVAL if constraint_set != 1, or any lo_i > hi_i or NaN bound
  * (synchronises the stream once for that check). */
 scg_status sketchycgal_set_constraints(scg_ctx* ctx, const double* lo, const double* hi);
+
+/* Radius r >= 0 (original units; scaled by 1/alpha like b) of the ball
+ * constraint set K = {u : ||u - b||_2 <= r} for a context initialised with
+ * params.constraint_set = 2; the projection is b + (u - b) min(1, r/||u - b||).
+ * Before the first sketchycgal_step (SCG_ESTATE otherwise); SCG_EINVAL for
+ * another constraint set or a negative or non-finite r.  Host-side only. */
+scg_status sketchycgal_set_ball(scg_ctx* ctx, double radius);
 
 /* Enqueue `iters` iterations of alg:sketchy-cgal (loop body: ApproxMinEvec by
  * randomized Lanczos, z, y and sketch updates).  Asynchronous: never

@@ -46,6 +46,7 @@ EXPORTS = [
     "sketchycgal_reconstruct", "sketchycgal_log", "sketchycgal_summary", "sketchycgal_get_state",
     "sketchycgal_set_state", "sketchycgal_lanczos_coeffs", "sketchycgal_apply", "sketchycgal_time_spmv",
     "sketchycgal_destroy", "scg_status_string", "sketchycgal_round", "sketchycgal_set_constraints",
+    "sketchycgal_set_ball",
     "scg_batch_workspace_size", "sketchycgal_batch_init", "sketchycgal_batch_step", "sketchycgal_batch_log",
     "sketchycgal_batch_summary", "sketchycgal_batch_get_state", "sketchycgal_batch_set_state", "sketchycgal_batch_reconstruct",
     "sketchycgal_batch_destroy", "sketchycgal_batch_round", "sketchycgal_batch_set_beta0",
@@ -91,6 +92,7 @@ def load() -> C.CDLL:
     lib.sketchycgal_batch_reconstruct.argtypes = [vp, i32, vp, vp, vp]
     lib.sketchycgal_round.argtypes = [vp, vp, vp, P(C.c_double), P(i32)]
     lib.sketchycgal_set_constraints.argtypes = [vp, vp, vp]
+    lib.sketchycgal_set_ball.argtypes = [vp, C.c_double]
     lib.sketchycgal_batch_round.argtypes = [vp, i32, vp, vp, P(C.c_double), P(i32)]
     lib.sketchycgal_batch_destroy.argtypes = [vp]
     lib.sketchycgal_batch_destroy.restype = None

@@ -40,7 +40,7 @@ class Params:
     basis_mode: int = 0           # 0: keep the Lanczos basis; 1: three vectors, basis regenerated
     omega_mode: int = 0           # 0: store the test matrix; 1: regenerate it from its counters
     trace_mode: int = 0           # 0: tr X = alpha; 1: tr X <= alpha
-    constraint_set: int = 0       # 0: diag X = b; 1: lo <= diag X <= hi (set_constraints)
+    constraint_set: int = 0       # 0: diag X = b; 1: lo <= diag X <= hi (set_constraints); 2: ball (set_ball)
 
     def to_c(self) -> _lib.scg_params:
         p = _lib.scg_params()
@@ -115,6 +115,10 @@ class SketchyCGAL:
         lo_t = None if lo is None else _dev(lo, torch.float64, self.device)
         hi_t = None if hi is None else _dev(hi, torch.float64, self.device)
         check(self.lib.sketchycgal_set_constraints(self.ctx, _ptr(lo_t), _ptr(hi_t)), "sketchycgal_set_constraints")
+
+    def set_ball(self, radius: float):
+        """Ball constraint set ||diag X - b|| <= radius (original units)."""
+        check(self.lib.sketchycgal_set_ball(self.ctx, float(radius)), "sketchycgal_set_ball")
 
     def step(self, iters: int = 1):
         check(self.lib.sketchycgal_step(self.ctx, iters), "sketchycgal_step")

@@ -72,7 +72,7 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.S = take(es * ld * R);
     L.rb = take(sizeof(int2) * (size_t)kSegMax * (n + 2));
     L.sc = take(sizeof(DevScalars));
-    const size_t pw = 15 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
+    const size_t pw = 19 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
     L.part = take(8 * (size_t)kGMax * pw);
     L.counter = take(256);
     L.logs = take(sizeof(scg_iter_log) * (size_t)p.T);
@@ -101,6 +101,8 @@ Prob<T> prob(scg_ctx* c) {
     P.b = c->b;
     P.lo = c->lo;
     P.hi = c->hi;
+    P.ball = (c->prm.constraint_set == 2) ? 1 : 0;
+    P.ball_r = c->ball_r;
     P.trace_mode = c->prm.trace_mode;
     P.z = c->z;
     P.y = c->y;
@@ -124,7 +126,9 @@ Prob<T> prob(scg_ctx* c) {
     P.p_ritz = pp + (size_t)kGMax * 8;
     P.p_obj = pp + (size_t)kGMax * (9 + kRMax);
     P.p_primal = pp + (size_t)kGMax * (11 + kRMax);
-    P.p_h = pp + (size_t)kGMax * (15 + kRMax);
+    P.p_ball = pp + (size_t)kGMax * (15 + kRMax);
+    P.p_ball2 = pp + (size_t)kGMax * (16 + kRMax);
+    P.p_h = pp + (size_t)kGMax * (19 + kRMax);
     P.G = c->G;
     P.Gs = c->Gs;
     P.logs = c->logs;
@@ -209,6 +213,12 @@ void enqueue_prep(scg_ctx* c, const IterArgs& it) {
     hipLaunchKernelGGL((k_prep<T>), dim3(c->G), dim3(kBlock), 0, c->stream, prob<T>(c), it);
 }
 
+// Ball constraint set: partial sums of ||z + y / beta - b||^2 for the slack.
+template <typename T>
+void enqueue_ball_norm(scg_ctx* c, double beta) {
+    hipLaunchKernelGGL((k_ball_norm<T>), dim3(c->G), dim3(kBlock), 0, c->stream, prob<T>(c), beta);
+}
+
 // Lanczos step i after its product: three-term update (accumulating the Ritz
 // vector in the second sweep of a regenerated basis), then the optional
 // reorthogonalisation against v_j0 .. v_i.
@@ -230,6 +240,7 @@ template <typename T>
 void enqueue_iteration(scg_ctx* c, int t) {
     const IterArgs it = iter_args(c, t);
     Prob<T> P = prob<T>(c);
+    if (P.ball) enqueue_ball_norm<T>(c, it.beta);
     enqueue_prep<T>(c, it);
     for (int i = 0; i < it.q; ++i) {
         launch_spmv<T, SPMV_LANCZOS>(c, basis_col<T>(c, i), i);
@@ -249,6 +260,10 @@ void enqueue_iteration(scg_ctx* c, int t) {
     launch_ritz<T>(c, it.q);
     launch_spmv<T, SPMV_OBJ>(c, (const T*)c->v, 0);
     hipLaunchKernelGGL((k_primal<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, it);
+    if (P.ball) {
+        enqueue_ball_norm<T>(c, it.beta_next);
+        hipLaunchKernelGGL((k_ball_r2<T>), dim3(c->G), dim3(kBlock), 0, c->stream, P, it);
+    }
     launch_dual_sketch<T>(c, it);
 }
 
@@ -724,7 +739,7 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (p->basis_mode == 1 && p->reorth == 2) return false;   // full reorthogonalisation needs the stored basis
     if (p->omega_mode != 0 && p->omega_mode != 1) return false;
     if (p->trace_mode != 0 && p->trace_mode != 1) return false;
-    if (p->constraint_set != 0 && p->constraint_set != 1) return false;
+    if (p->constraint_set < 0 || p->constraint_set > 2) return false;
     return true;
 }
 
@@ -853,6 +868,13 @@ scg_status sketchycgal_set_constraints(scg_ctx* c, const double* lo, const doubl
         HIP_TRY(hipStreamSynchronize(c->stream));
         return SCG_EINVAL;
     }
+    return SCG_OK;
+}
+
+scg_status sketchycgal_set_ball(scg_ctx* c, double radius) {
+    if (!c || c->prm.constraint_set != 2 || !(radius >= 0.0) || !std::isfinite(radius)) return SCG_EINVAL;
+    if (c->t_next != 1) return SCG_ESTATE;
+    c->ball_r = radius * (c->prm.scale ? 1.0 / c->alpha_orig : 1.0);   // scaled like b (k_scatter)
     return SCG_OK;
 }
 

@@ -55,6 +55,8 @@ struct Prob {
     const double* b;      // scaled b
     const double* lo;     // box constraint set (scaled), or null: K = {b}
     const double* hi;
+    int ball;             // 1: K is the ball {||u - b|| <= ball_r} (l2), centred at b
+    double ball_r;        // its radius, scaled
     int trace_mode;       // 0: tr X = alpha; 1: tr X <= alpha
     double* z;
     double* y;
@@ -78,6 +80,8 @@ struct Prob {
     double* p_ritz;       // k_ritz,        G  x (RB + 1)
     double* p_obj;        // k_spmv OBJ,    Gs x 2
     double* p_primal;     // k_primal,      G  x 4
+    double* p_ball;       // k_ball_norm,   G  x 1
+    double* p_ball2;      // k_ball_r2,     G  x 3
     double* p_h;          // k_reorth_dot,  G  x (step + 1)
     int G;                // workgroups of the vector kernels
     int Gs;               // workgroups of the SpMV kernels
@@ -136,6 +140,7 @@ struct scg_ctx {
     scg_iter_log* logs;
     double* recon;   // reconstruction scratch (n x R FP64 and small matrices)
     double* racc;    // FP64 Ritz accumulator (regenerated basis), else null
+    double ball_r;   // radius of the ball constraint set, scaled (constraint_set = 2)
     double* lo;      // box constraint set, scaled (constraint_set = 1), else null
     double* hi;
     size_t recon_bytes;

@@ -666,6 +666,65 @@ __global__ __launch_bounds__(kBlock) void k_ritz_fin(DevScalars* sc, const doubl
 // Euclidean projection onto the box [lo, hi] (Appendix D.3), entrywise.
 __device__ __forceinline__ double box_proj(double u, double lo, double hi) { return fmin(fmax(u, lo), hi); }
 
+// Ball constraint set {||u - b|| <= r}: the projection of u is
+// b + (u - b) min(1, r / ||u - b||); ||u - b||^2 comes from k_ball_norm's partials.
+template <typename T>
+__device__ __forceinline__ double ball_factor(const Prob<T>& P) {
+    double tot[1];
+    reduce_partials<1>(P.p_ball, P.G, tot);
+    const double nd = sqrt(tot[0]);
+    return (nd <= P.ball_r) ? 1.0 : P.ball_r / nd;
+}
+
+// Partial sums of ||z + y / beta - b||^2 (the point the ball slack projects).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ball_norm(Prob<T> P, double beta) {
+    const int64_t n = P.n;
+    double a = 0.0;
+    SCG_FOR_QUADS(n) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        double z4[4], y4[4], b4[4];
+        ld4(P.z + r, m, z4);
+        ld4(P.y + r, m, y4);
+        ld4(P.b + r, m, b4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double d = (j < m) ? (z4[j] + y4[j] / beta) - b4[j] : 0.0;
+            a += d * d;
+        }
+    }
+    double v[1] = {a};
+    write_partials<1>(v, P.p_ball);
+}
+
+// Ball, after the primal update: with w_bar = b + cb (z + y / beta_{t+1} - b),
+// partial sums of ||z - w_bar||^2, ||y||^2 and y^T (z - w_bar).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ball_r2(Prob<T> P, IterArgs it) {
+    const int64_t n = P.n;
+    const double cb = ball_factor(P);
+    double a[3] = {0.0, 0.0, 0.0};
+    SCG_FOR_QUADS(n) {
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+        double z4[4], y4[4], b4[4];
+        ld4(P.z + r, m, z4);
+        ld4(P.y + r, m, y4);
+        ld4(P.b + r, m, b4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j < m) {
+                const double d = z4[j] - (b4[j] + cb * ((z4[j] + y4[j] / it.beta_next) - b4[j]));
+                a[0] += d * d;
+                a[1] += y4[j] * y4[j];
+                a[2] += y4[j] * d;
+            }
+        }
+    }
+    write_partials<3>(a, P.p_ball2);
+}
+
 // Shift, start vector, and partial sums of the state before the update.
 // Box constraint set: the shift uses the slack w = proj_K(z + y / beta) in
 // place of b (alg:full-sketchy-cgal-supp).
@@ -677,6 +736,8 @@ __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
         sc->k = 0;
     }
     const int64_t n = P.n;
+    double cb = 0.0;   // ball: the slack is b + cb (z + y / beta - b)
+    if (P.ball) cb = ball_factor(P);
     double a[kWPrep] = {0, 0, 0, 0, 0, 0};
     SCG_FOR_QUADS(n) {
         const int64_t r = 4 * qd;
@@ -694,7 +755,8 @@ __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const double zb = z4[j] - b4[j];
-            const double zw = P.lo ? z4[j] - box_proj(z4[j] + y4[j] / it.beta, lo4[j], hi4[j]) : zb;
+            const double zw = P.lo ? z4[j] - box_proj(z4[j] + y4[j] / it.beta, lo4[j], hi4[j])
+                                   : (P.ball ? z4[j] - (b4[j] + cb * ((z4[j] + y4[j] / it.beta) - b4[j])) : zb);
             s4[j] = d4[j] + (y4[j] + it.beta * zw);
             if (j < m) {
                 a[1] += y4[j] * b4[j];
@@ -799,11 +861,18 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
     if (qd < qhi) load(4 * qd, quad_rows(4 * qd, n));   // first quad in flight before the reduction
     double tot[kWPrimal];
     reduce_partials<kWPrimal>(P.p_primal, P.G, tot);
-    const double r2 = tot[0];
+    // ball: ||z - w_bar||^2, ||y||^2, y^T (z - w_bar) from k_ball_r2, and the slack factor
+    double cb = 0.0, tb[3] = {0.0, 0.0, 0.0};
+    if (P.ball) {
+        cb = ball_factor(P);
+        reduce_partials<3>(P.p_ball2, P.G, tb);
+    }
+    const double r2 = P.ball ? tb[0] : tot[0];
     double gamma = (r2 == 0.0) ? it.beta0
                                : fmin(it.beta0, 4.0 * it.alpha * it.alpha * it.beta0 / (pow(it.t + 1.0, 1.5) * r2));
     if (isfinite(it.K)) {
-        const double ny2 = tot[1] + 2.0 * gamma * tot[2] + gamma * gamma * r2;
+        const double ny2 = P.ball ? tb[1] + 2.0 * gamma * tb[2] + gamma * gamma * r2
+                                  : tot[1] + 2.0 * gamma * tot[2] + gamma * gamma * r2;
         if (sqrt(fmax(ny2, 0.0)) > it.K) gamma = 0.0;
     }
     const double iv = sc->inv_vnorm;
@@ -815,7 +884,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
         const double p_old = sc->p;
         const double xi = sc->xi;
         // the stopping quantities are those of the model problem (diag X = b, tr X = alpha)
-        const bool model = !box && P.trace_mode == 0;
+        const bool model = !box && !P.ball && P.trace_mode == 0;
         const double stop_obj =
             model ? (p_old + sc->d_yb + 0.5 * it.beta * sc->d_zz - it.alpha * xi) / (1.0 + fabs(p_old)) : NAN;
         const double gap = p_old + sc->d_gapdot - (hon ? it.alpha * xi : 0.0);
@@ -833,7 +902,8 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
             L.xi = xi;
             L.cv = sc->cv;
             L.p = p_new;
-            L.infeas = box ? sqrt(tot[3]) : sqrt(r2);
+            // dist_K(z_{t+1}): the box from k_primal, the ball in closed form
+            L.infeas = box ? sqrt(tot[3]) : (P.ball ? fmax(0.0, sqrt(tot[0]) - P.ball_r) : sqrt(r2));
             L.gamma = gamma;
             L.gap = gap;
             L.stop_obj = stop_obj;
@@ -854,7 +924,8 @@ __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) 
         const int m = quad_rows(r, n);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const double wb = box ? box_proj(z4[j] + y4[j] / it.beta_next, lo4[j], hi4[j]) : b4[j];
+            const double wb = box ? box_proj(z4[j] + y4[j] / it.beta_next, lo4[j], hi4[j])
+                                  : (P.ball ? b4[j] + cb * ((z4[j] + y4[j] / it.beta_next) - b4[j]) : b4[j]);
             y4[j] += gamma * (z4[j] - wb);
             v4[j] = ea * (v4[j] * iv);
         }

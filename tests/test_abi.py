@@ -57,7 +57,7 @@ def test_workspace_size_and_validation():
            dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=3), dict(reorth=-1), dict(precision=7), dict(n=0),
            dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_grid=-1), dict(spmv_grid=4096),
            dict(q_mode=1, q_fixed=600, n=10_000), dict(basis_mode=2), dict(basis_mode=-1), dict(omega_mode=2),
-           dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=2)]
+           dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=3), dict(constraint_set=-1)]
     for kw in bad:
         st, _ = _ws(**dict(kw))
         assert st == _lib.SCG_EINVAL, kw
@@ -98,6 +98,7 @@ def test_box_constraint_set_adds_two_vectors():
     assert 16 * n <= b1 - b0 <= 16 * n + 2 * 256
     lib = _lib.load()
     assert lib.sketchycgal_set_constraints(None, None, None) == _lib.SCG_EINVAL
+    assert lib.sketchycgal_set_ball(None, 1.0) == _lib.SCG_EINVAL
 
 
 def test_init_rejects_null_and_misaligned_arguments():

@@ -1,7 +1,8 @@
 """General template on the GPU (Appendix D, alg:full-sketchy-cgal-supp) with the
-diagonal constraint map: a box constraint set K = {lo <= diag X <= hi} and the
-trace-bounded set tr X <= alpha, against the oracle's general template (pinned
-in test_oracle_general.py) and against the equality model it contains.
+diagonal constraint map: a box constraint set K = {lo <= diag X <= hi}, the l2
+ball K = {||diag X - b|| <= r}, and the trace-bounded set tr X <= alpha, against
+the oracle's general template (pinned in test_oracle_general.py) and against
+the equality model it contains.
 """
 import dataclasses
 import math
@@ -168,10 +169,12 @@ def test_set_constraints_errors_and_recovery(cfg1):
 
 def test_general_template_at_full_size_fp64():
     # the 1M-vertex torus, tr X <= alpha and diag X <= 1, two iterations of the
-    # paper's q_t schedule against the oracle
+    # paper's q_t schedule against the oracle, with full reorthogonalisation
+    # (the recurrence without it follows rounding from the second iteration
+    # at this size; test_oracle_floor.py)
     need_gpu()
     inst = synth.config_instance(2)
-    kw = dict(R=10, T=2, seed=synth.CONFIG_SEEDS[2], trace_mode=1)
+    kw = dict(R=10, T=2, seed=synth.CONFIG_SEEDS[2], trace_mode=1, reorth=2)
     hi = np.ones(inst.n)
     announce(f"general template full size n={inst.n}")
     s = _solver(inst, hi=hi, **kw)
@@ -184,3 +187,77 @@ def test_general_template_at_full_size_fp64():
     g = s.get_state()
     assert maxrel(g["z"].cpu().numpy(), ref.z) < 1e-8
     assert maxrel(g["y"].cpu().numpy(), ref.y) < 1e-8
+
+
+def _ball_solver(inst, radius=None, **kw):
+    s = make_solver(inst, constraint_set=2, **kw)
+    if radius is not None:
+        s.set_ball(radius)
+    return s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ball_of_radius_zero_is_bitwise_the_equality_model(cfg1, precision):
+    need_gpu()
+    kw = dict(R=10, T=30, seed=SEED1, q_mode=1, q_fixed=12, precision=precision)
+    a = make_solver(cfg1, **kw)
+    a.run()
+    la = a.log()
+    for b in (_ball_solver(cfg1, 0.0, **kw), _ball_solver(cfg1, **kw)):
+        b.run()
+        lb = b.log()
+        for key in EXACT:
+            assert np.array_equal(la[key], lb[key]), key
+        assert np.all(np.isnan(lb["stop_obj"]))
+        ga, gb = a.get_state(), b.get_state()
+        for key in ("z", "y", "S"):
+            assert np.array_equal(ga[key].cpu().numpy(), gb[key].cpu().numpy()), key
+
+
+@pytest.mark.parametrize("trace_mode", [0, 1])
+def test_ball_trajectory_matches_oracle(cfg1, trace_mode):
+    need_gpu()
+    kw = dict(R=10, T=40, seed=SEED1, q_mode=1, q_fixed=8, trace_mode=trace_mode)
+    radius = 5.0                      # ||b|| = 28.3: the ball is active
+    announce(f"ball radius={radius} trace_mode={trace_mode}")
+    s = _ball_solver(cfg1, radius, **kw)
+    s.run()
+    lg = s.log()
+    ref = sketchy_cgal_ball(cfg1, radius, **kw)
+    assert lg["k"].tolist() == ref.log["k"].tolist()
+    assert maxrel(lg["p"], ref.log["p"]) < 1e-9
+    assert np.max(np.abs(lg["infeas"] - ref.log["infeas"]) / np.maximum(ref.log["infeas"], 1e-12)) < 1e-9
+    for key in ("xi", "gap", "gamma", "cv"):
+        assert np.max(np.abs(lg[key] - ref.log[key]) / np.maximum(np.abs(ref.log[key]), 1e-12)) < 1e-8, key
+    g = s.get_state()
+    assert maxrel(g["z"].cpu().numpy(), ref.z) < 1e-9
+    assert maxrel(g["y"].cpu().numpy(), ref.y) < 1e-9
+    summ = s.summary()
+    assert rel(summ["objective"], ref.objective) < 1e-9
+    assert rel(summ["infeasibility"], ref.infeasibility) < 1e-9
+    assert np.any(ref.log["infeas"] > 0)   # the ball constraint was violated at some iterate
+
+
+def sketchy_cgal_ball(inst, radius, **kw):
+    from gpu_util import oracle_params
+    from oracle import sketchy_cgal
+    return sketchy_cgal(inst.to_scipy(), inst.b, oracle_params(**kw), radius=radius)
+
+
+def test_set_ball_errors(cfg1):
+    need_gpu()
+    from paper_1912_02949_amd._lib import SCGError, SCG_EINVAL, SCG_ESTATE
+    kw = dict(R=4, T=5, seed=SEED1, q_mode=1, q_fixed=6)
+    s = make_solver(cfg1, **kw)
+    with pytest.raises(SCGError) as e:
+        s.set_ball(1.0)
+    assert e.value.status == SCG_EINVAL
+    s = make_solver(cfg1, constraint_set=2, **kw)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(SCGError) as e:
+            s.set_ball(bad)
+        assert e.value.status == SCG_EINVAL
+    s.step(1)
+    with pytest.raises(SCGError) as e:
+        s.set_ball(1.0)
+    assert e.value.status == SCG_ESTATE
