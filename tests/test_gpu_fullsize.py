@@ -115,3 +115,35 @@ def test_torus_two_iterations_full_reorth_at_full_size(precision):
             assert maxrel(lg[key], ref.log[key]) < 1e-9, key
         assert maxrel(g["z"].cpu().numpy(), ref.z) < 1e-9
         assert maxrel(g["y"].cpu().numpy(), ref.y) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_workload_at_full_size(precision):
+    # the 256-problem batch of the benchmark in its launch configuration; the
+    # largest, the median and the smallest problem against the oracle run on it
+    # alone.  FP64, two iterations: the oracle's own floor on these three
+    # (reversed row sums) is <= 1.2e-9 on p and ||z - b||, 2.6e-9 on z; bars
+    # at about 100x.  FP32-stream: its one-iteration floor.
+    need_gpu()
+    from paper_1912_02949_amd import BatchedSketchyCGAL, Params
+    insts = synth.batched_erdos_renyi(256, 200, 20000, 8)
+    T = 2 if precision == "fp64" else 1
+    kw = dict(R=8, T=T, seed=synth.CONFIG_SEEDS[4], precision=precision)
+    announce(f"batched workload at full size {precision}")
+    bt = BatchedSketchyCGAL(insts, Params(**kw))
+    bt.run()
+    order = np.argsort([g.n for g in insts])
+    for i in (int(order[-1]), int(order[len(order) // 2]), int(order[0])):
+        ref = oracle_run(insts[i], instance=i, **kw)
+        lg = bt.log(i)
+        z = bt.get_state(i)["z"].cpu().numpy()
+        assert lg["k"].tolist() == ref.log["k"].tolist(), i
+        assert abs(z.sum() - 1.0) < 1e-9 and z.min() >= 0.0, i
+        if precision == "fp64":
+            assert maxrel(lg["p"], ref.log["p"]) < 1e-7, i
+            assert maxrel(lg["infeas"], ref.log["infeas"]) < 1e-7, i
+            assert maxrel(z, ref.z) < 3e-7, i
+        else:
+            assert rel(lg["p"][0], ref.log["p"][0]) < 1e-4, i
+            assert rel(lg["xi"][0], ref.log["xi"][0]) < 2e-2, i
+            assert rel(lg["infeas"][0], ref.log["infeas"][0]) < 1e-2, i
