@@ -146,14 +146,14 @@ class Solve:
         self.lib.sketchycgal_summary(self.ctx, C.byref(s))
         return {k: getattr(s, k) for k, _ in _lib.scg_summary._fields_}
 
-    def last_record(self):
-        """The last iteration's log record (scaled units), as a dict."""
+    def record(self, which: int = -1):
+        """One iteration's log record (scaled units) as a dict: the last by default, 0 for t = 1."""
         from paper_1912_02949_amd import _lib
         cap = self.prm.T
         arr = (_lib.scg_iter_log * cap)()
         cnt = C.c_int32()
         _lib.check(self.lib.sketchycgal_log(self.ctx, arr, cap, C.byref(cnt)), "log")
-        rec = arr[cnt.value - 1]
+        rec = arr[which if which >= 0 else cnt.value + which]
         return {k: getattr(rec, k) for k, _ in _lib.scg_iter_log._fields_}
 
     def infeasibility_log(self):
@@ -397,7 +397,8 @@ def main():
     progress(f"fp32 solves: {1e3 * dt32 / args.steps:.1f} ms each")
     sum32 = s32.summary()
     infeas32 = s32.infeasibility_log()
-    last32 = s32.last_record()
+    last32 = s32.record()
+    first32 = s32.record(0)
     norm_b = math.sqrt(float((inst.b * inst.b).sum()))
     cut_w, cut_j, cut_s = s32.round_cut()
     # SpMV kernel leg: back-to-back launches on the solver's stream, HIP events
@@ -424,7 +425,8 @@ def main():
         dt64 = timed(s64, args.steps, args.warmup, torch)
         progress(f"fp64 solves: {1e3 * dt64 / args.steps:.1f} ms each")
         sum64 = s64.summary()
-        last64 = s64.last_record()
+        last64 = s64.record()
+        first64 = s64.record(0)
         s64.close()
         fp64 = {
             "value": args.steps * T / dt64,
@@ -433,6 +435,7 @@ def main():
             "infeasibility": sum64["infeasibility"],
             "infeasibility_rel": sum64["infeasibility"] / norm_b,
             "eigen_residual_scaled": last64["resid"],
+            "first_iteration_p_scaled": first64["p"],
         }
         # speedup at equal final infeasibility: the FP32 solve stopped at the first iteration whose
         # ||diag X - b|| is at most the FP64 solve's final value, timed as a whole solve
@@ -527,6 +530,11 @@ def main():
                         "eigen_residual_scaled": last32["resid"], "xi_scaled": last32["xi"],
                         "objective_rel_diff_vs_fp64": (abs(sum32["objective"] - fp64["objective"]) /
                                                        abs(fp64["objective"])) if fp64 else None,
+                        # from the same (zero) state: the per-iteration FP32-stream error, which
+                        # the whole-run difference above compounds through rounding-sensitive iterates
+                        "first_iteration_objective_rel_diff_vs_fp64": (
+                            abs(first32["p"] - fp64["first_iteration_p_scaled"]) /
+                            abs(fp64["first_iteration_p_scaled"])) if fp64 else None,
                         "rounded_cut_weight": cut_w, "rounded_cut_column": cut_j, "rounding_ms": 1e3 * cut_s,
                         "cut_over_sdp_objective": cut_w / -sum32["objective"]},
         "storage_optimal_fp32": storage,
