@@ -74,7 +74,7 @@ typedef struct {
     int32_t  trace_correct; /* 1: trace-correct Lambda in reconstruct (alg:sketchy-cgal)     */
     int32_t  reorth;        /* 0: Lanczos as in alg:rand-lanczos; 1: local reorthogonalisation
                                (one Gram-Schmidt pass against v_{i-1}, v_i); 2: full (against
-                               every stored vector).  The batched engine takes 0 or 2          */
+                               every stored vector)                                           */
     int32_t  precision;     /* scg_precision                                                 */
     int32_t  instance;      /* Philox counter word selecting this problem's random streams   */
     int32_t  matrix_format; /* 0: compress the off-diagonal values when they share one

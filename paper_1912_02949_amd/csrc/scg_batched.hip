@@ -533,10 +533,12 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
                 }
             }
         }
-        if (A.reorth == 2) {
+        if (A.reorth != 0) {
             __syncthreads();   // w was written quad-wise by other threads
-            // h_j = v_hat_j^T w for j <= i, eight at a time, then w <- w - sum_j h_j v_hat_j
-            for (int jb = 0; jb <= i; jb += 8) {
+            // h_j = v_hat_j^T w for j0 <= j <= i (j0 = 0: full, i - 1: local), eight at a
+            // time, then w <- w - sum_j h_j v_hat_j
+            const int j0 = (A.reorth == 2) ? 0 : (i > 0 ? i - 1 : 0);
+            for (int jb = j0; jb <= i; jb += 8) {
                 double hacc[8];
 #pragma unroll
                 for (int jj = 0; jj < 8; ++jj) hacc[jj] = 0.0;
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
             acc2[0] = 0.0;
             for (int p = tid; p < n; p += kBT) {
                 double a = 0.0;
-                for (int j = 0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + p];
+                for (int j = j0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + p];
                 const T wt = (T)((double)w[p] - a);
                 w[p] = wt;
                 xl[p] = wt;
@@ -721,8 +723,9 @@ __global__ __launch_bounds__(kBT) void k_batch_iter(BatchArgs<T, CT> A) {
             w[r] = wt;
             acc2[0] += (double)wt * (double)wt;
         }
-        if (A.reorth == 2) {
-            for (int jb = 0; jb <= i; jb += 8) {
+        if (A.reorth != 0) {
+            const int j0 = (A.reorth == 2) ? 0 : (i > 0 ? i - 1 : 0);   // full or local
+            for (int jb = j0; jb <= i; jb += 8) {
                 double hacc[8];
 #pragma unroll
                 for (int jj = 0; jj < 8; ++jj) hacc[jj] = 0.0;
@@ -737,7 +740,7 @@ __global__ __launch_bounds__(kBT) void k_batch_iter(BatchArgs<T, CT> A) {
             acc2[0] = 0.0;
             for (int r = tid; r < n; r += kBT) {
                 double a = 0.0;
-                for (int j = 0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + r];
+                for (int j = j0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + r];
                 const T wt = (T)((double)w[r] - a);
                 w[r] = wt;
                 acc2[0] += (double)wt * (double)wt;
@@ -1371,7 +1374,7 @@ bool bparams_ok(const scg_params* p, int ninst, const int64_t* inst_n) {
     if (p->R < 1 || p->R > kRMax || p->T < 1 || !(p->beta0 > 0.0) || !(p->K >= 0.0)) return false;
     if (p->q_mode != 0 && p->q_mode != 1) return false;
     if (p->q_mode == 1 && p->q_fixed < 1) return false;
-    if (p->reorth != 0 && p->reorth != 2) return false;
+    if (p->reorth < 0 || p->reorth > 2) return false;
     if (p->precision != SCG_FP64 && p->precision != SCG_FP32_STREAM) return false;
     if (p->matrix_format != 0 && p->matrix_format != 1) return false;
     if (p->basis_mode != 0 || p->omega_mode != 0) return false;   // the batch keeps both in HBM

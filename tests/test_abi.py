@@ -136,7 +136,7 @@ def test_batch_workspace_size_and_validation():
     assert st2 == _lib.SCG_OK and b2 < b
     st3, b3 = _bws([200, 5000, 20000, 300])
     assert st3 == _lib.SCG_OK and b3 > b
-    for sizes, kw in [([200, 5], {}), ([], {}), ([100], dict(reorth=1)), ([100], dict(T=0)),
+    for sizes, kw in [([200, 5], {}), ([], {}), ([100], dict(reorth=3)), ([100], dict(T=0)),
                       ([1000], dict(q_mode=1, q_fixed=129)), ([100], dict(precision=3)), ([100], dict(R=33)),
                       ([100], dict(basis_mode=1)), ([100], dict(omega_mode=1)), ([100], dict(trace_mode=1)),
                       ([100], dict(constraint_set=1))]:

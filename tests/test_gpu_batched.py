@@ -105,12 +105,18 @@ def test_batched_set_beta0_errors():
     assert e.value.status == SCG_ESTATE
 
 
-@pytest.mark.parametrize("which", ["unit", "weighted"])
-def test_batched_single_iteration_from_oracle_state_fp64(which):
+@pytest.mark.parametrize("which,reorth,q", [("unit", 2, 36), ("weighted", 2, 36), ("unit", 1, 8)])
+def test_batched_single_iteration_from_oracle_state_fp64(which, reorth, q):
     need_gpu()
-    kw = dict(R=8, T=40, seed=SEED4, q_mode=1, q_fixed=36, reorth=2)
+    kw = dict(R=8, T=40, seed=SEED4, q_mode=1, q_fixed=q, reorth=reorth)
     insts = small_batch() if which == "unit" else valued_batch()
     bt = make_batch(insts, **kw)
+    # full reorthogonalisation: the oracle reproduces itself to 1e-12 here, bar
+    # 1e-9 (S 1e-8).  Local (reorth = 1, q = 8): at t = 2 the Ritz vector of the
+    # 2500-vertex problem is unconverged, and a 1-ulp change of the start vector
+    # (three draws) moves the oracle's own p by 2.2e-9, ||z - b|| by 1.0e-8, xi
+    # by 9.2e-9, z by 2.1e-8 and S by 1.2e-5; bars at about 10x: 2e-7, S 1e-4.
+    tol, tol_s = (1e-9, 1e-8) if reorth == 2 else (2e-7, 1e-4)
     for t in (2, 25):
         refs = []
         for i, inst in enumerate(insts):
@@ -125,12 +131,12 @@ def test_batched_single_iteration_from_oracle_state_fp64(which):
             lg = bt.log(i)
             assert g["t"] == t + 1
             assert lg["k"][t - 1] == ref.log["k"][-1], (t, i)
-            assert rel(g["p"], ref.p) < 1e-9, (t, i)
-            assert rel(lg["infeas"][t - 1], ref.log["infeas"][-1]) < 1e-9, (t, i)
-            assert rel(lg["xi"][t - 1], ref.log["xi"][-1]) < 1e-9, (t, i)
-            assert maxrel(g["z"].cpu().numpy(), ref.z) < 1e-9, (t, i)
-            assert maxrel(g["y"].cpu().numpy(), ref.y) < 1e-9, (t, i)
-            assert maxrel(g["S"].cpu().numpy(), ref.S) < 1e-8, (t, i)
+            assert rel(g["p"], ref.p) < tol, (t, i)
+            assert rel(lg["infeas"][t - 1], ref.log["infeas"][-1]) < tol, (t, i)
+            assert rel(lg["xi"][t - 1], ref.log["xi"][-1]) < tol, (t, i)
+            assert maxrel(g["z"].cpu().numpy(), ref.z) < tol, (t, i)
+            assert maxrel(g["y"].cpu().numpy(), ref.y) < tol, (t, i)
+            assert maxrel(g["S"].cpu().numpy(), ref.S) < tol_s, (t, i)
             assert rel(g["tau"], ref.tau) < 1e-12, (t, i)
 
 
@@ -265,7 +271,7 @@ def test_batched_validation_errors():
         make_batch([bad] + insts[1:], R=8, T=10, seed=1)
     assert e.value.status == SCG_EINVAL
     with pytest.raises(SCGError):
-        make_batch(insts, R=8, T=10, seed=1, reorth=1)
+        make_batch(insts, R=8, T=10, seed=1, reorth=3)
     with pytest.raises(SCGError):
         make_batch(insts + [synth.laplacian_instance(synth.cycle(5))], R=8, T=10, seed=1)
     bt = make_batch(insts, R=8, T=10, seed=1, q_mode=1, q_fixed=6)
