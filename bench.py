@@ -41,9 +41,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # SpMV shapes whose HBM traffic the profile records: (lanes per row, workgroups cap, column segments);
-# workgroups 0 = one row-block range per wave
+# workgroups 0 = one row-block range per wave; lanes 1 = the quad-chunk product (k_spmvq)
 PROBE_SHAPES = {
-    2: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2)),
+    2: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2), (1, 1536, 1), (1, 2048, 1)),
     5: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)),
 }
 TRAFFIC_FILES = {
@@ -67,6 +67,11 @@ def measured_traffic(k: int, summ: dict):
             return sh["hbm_bytes_per_launch"]
     return None
 KERNEL_SOURCES = ["scg_kernels.hpp", "scg_device.hpp", "scg_internal.hpp"]
+
+
+def spmv_kernel_name(summ: dict) -> str:
+    """The product kernel the autotuner chose: lanes 1 is the quad-chunk layout."""
+    return "k_spmvq" if summ["spmv_lanes"] == 1 else "k_spmv"
 
 
 def kernel_source_sha() -> str:
@@ -270,7 +275,8 @@ def spmv_line(torch, k: int, precision: str):
     gbs = by / (ms.value * 1e-3) / 1e9
     return {"n": inst.n, "nnz_offdiag": nnz_off, "avg_launch_us": ms.value * 1e3, "algorithmic_bytes_per_launch": by,
             "traffic": measured_traffic(k, summ) if precision == "fp32" else None,
-            "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "lanes_per_row": summ["spmv_lanes"],
+            "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "kernel": spmv_kernel_name(summ),
+            "lanes_per_row": summ["spmv_lanes"],
             "column_segments": summ["spmv_segments"], "workgroups": summ["spmv_grid"],
             "matrix_format": ["values", "columns only", "columns with sign bit"][summ["matrix_format"]]}
 
@@ -503,7 +509,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_spmv (Lanczos SpMV with diagonal shift, FP32)",
+            "kernel": spmv_kernel_name(sum32) + " (Lanczos SpMV with diagonal shift, FP32)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -520,7 +526,8 @@ def main():
                                                "an n-entry FP32 vector on the same GPU (the SpMV makes one gather per "
                                                "off-diagonal entry; half of the torus's are local, none here)",
         },
-        "spmv_tuning": {"lanes_per_row": sum32["spmv_lanes"], "column_segments": sum32["spmv_segments"],
+        "spmv_tuning": {"kernel": spmv_kernel_name(sum32), "lanes_per_row": sum32["spmv_lanes"],
+                        "column_segments": sum32["spmv_segments"],
                         "workgroups": sum32["spmv_grid"],
                         "matrix_format": ["values", "columns only", "columns with sign bit"][sum32["matrix_format"]]},
         "fp64_plain": fp64,

@@ -84,7 +84,13 @@ typedef struct {
     int32_t  segments;      /* column segments of the SpMV: 0 = chosen by the autotuner
                                (1 below 1M nonzeros), or 1, 2, 4                              */
     int32_t  spmv_lanes;    /* lanes per row of the SpMV reduction: 0 = autotuned / by mean
-                               row length, or 2, 4, 8, 16, 32                                 */
+                               row length, or 2, 4, 8, 16, 32; 1 = the quad-chunk product
+                               (each row's column words padded to 16-byte quads, rows packed
+                               into chunks of 64 quads, one chunk per wave, rows summed by a
+                               lane scan): only for compressed formats (matrix_format 0 with
+                               one off-diagonal magnitude) and rows of at most 128
+                               off-diagonal entries, one column segment; init returns
+                               SCG_EINVAL when the matrix does not qualify                    */
     int32_t  spmv_grid;     /* SpMV workgroups: 0 = autotuned / one row-block range per wave,
                                or a cap (rounded to a multiple of 8, at most 2048)            */
     int32_t  basis_mode;    /* Lanczos basis storage: 0 = all q+1 vectors kept (ld x (q+1)),
@@ -245,7 +251,12 @@ scg_status sketchycgal_lanczos_coeffs(scg_ctx* ctx, double* omega, double* rho, 
 scg_status sketchycgal_apply(scg_ctx* ctx, const double* x, double* y);
 
 /* Average duration (ms) of `reps` back-to-back launches of the Lanczos SpMV
- * kernel on the context's stream, timed with HIP events on that stream. */
+ * kernel on the context's stream, timed with HIP events on that stream.  The
+ * launches are the product of Lanczos step 1 (the form every step after the
+ * first takes: it reduces the preceding update's partial sums), after the
+ * shift, the start vector, one product and one update of the next iteration
+ * have been formed.  Overwrites the per-iteration scratch (Lanczos vectors,
+ * product, coefficients); z, y, S, p and tau are untouched.  Synchronises. */
 scg_status sketchycgal_time_spmv(scg_ctx* ctx, int32_t reps, double* avg_ms);
 
 void sketchycgal_destroy(scg_ctx* ctx);

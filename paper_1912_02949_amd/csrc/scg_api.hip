@@ -43,8 +43,21 @@ int qmax_for(const scg_params& p, int64_t n) {
 
 size_t elem_size(const scg_params& p) { return p.precision == SCG_FP32_STREAM ? 4 : 8; }
 
+// Chunks of the quad-chunk SpMV layout to reserve (0: that layout is never
+// used with these parameters).  A row takes max(1, ceil(d / 4)) quads and
+// rows of at most kQRowMax entries (32 quads) are packed whole into chunks
+// of 64 quads; a chunk is closed only when the next row does not fit, so
+// every chunk but the last holds at least 33 quads.  The sum over rows is at
+// most nnz / 4 + n quads.
+int64_t quad_chunk_cap(const scg_params& p, int64_t n, int64_t nnz) {
+    if (p.matrix_format == 1 || (p.spmv_lanes != 0 && p.spmv_lanes != 1) || p.segments > 1) return 0;
+    if (n >= ((int64_t)1 << 29)) return 0;   // columns must fit the 29-bit field
+    const int64_t dq = nnz / 4 + n + 1;
+    return dq / 33 + 2;
+}
+
 struct Layout {
-    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, total;
+    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, qw, qc, total;
     size_t recon_bytes;
 };
 
@@ -81,6 +94,9 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.racc = take(p.basis_mode == 1 ? 8 * ld : 0);
     L.lo = take(p.constraint_set == 1 ? 8 * (size_t)n : 0);   // box constraint set, scaled
     L.hi = take(p.constraint_set == 1 ? 8 * (size_t)n : 0);
+    const int64_t nqc = quad_chunk_cap(p, n, nnz);
+    L.qw = take(sizeof(int32_t) * 256 * (size_t)nqc);
+    L.qc = take(sizeof(int2) * (size_t)nqc);
     L.total = off;
     return L;
 }
@@ -118,6 +134,9 @@ Prob<T> prob(scg_ctx* c) {
     P.S = (T*)c->S;
     P.rb = c->rb;
     P.nrb = c->nrb;
+    P.qw = c->qw;
+    P.qc = c->qc;
+    P.nqc = c->nqc;
     P.sc = c->sc;
     double* pp = c->part;
     P.p_prep = pp;
@@ -155,6 +174,12 @@ void launch_spmv_f(scg_ctx* c, const T* x, int step, int lanes) {
 template <typename T, int MODE>
 void launch_spmv(scg_ctx* c, const T* x, int step, int lanes = 0) {
     if (lanes == 0) lanes = c->lanes;
+    if (lanes == 1) {   // the quad-chunk product (column-word formats only)
+        const dim3 g(c->Gs), b(kBlock);
+        if (c->fmt == FMT_PAT) hipLaunchKernelGGL((k_spmvq<T, MODE, FMT_PAT>), g, b, 0, c->stream, prob<T>(c), x, step);
+        else hipLaunchKernelGGL((k_spmvq<T, MODE, FMT_SGN>), g, b, 0, c->stream, prob<T>(c), x, step);
+        return;
+    }
     if (c->fmt == FMT_PAT) launch_spmv_f<T, MODE, 8, FMT_PAT>(c, x, step, lanes);
     else if (c->fmt == FMT_SGN) launch_spmv_f<T, MODE, 8, FMT_SGN>(c, x, step, lanes);
     else launch_spmv_f<T, MODE, 8, FMT_VAL>(c, x, step, lanes);
@@ -553,14 +578,86 @@ scg_status build_segments(scg_ctx* c, int nseg, const int64_t* row_ptr, const in
     return SCG_OK;
 }
 
-// Autotuner: time the Lanczos SpMV for each lanes-per-row choice on this
-// matrix (after a k_prep of iteration 1 has filled the start vector and the
-// shift) and keep the fastest.  Timed with HIP events on the context stream.
-// and each column-segment count, and keep the fastest layout.
+// Column words of the quad-chunk layout: row r's off-diagonal entries (input
+// order, diagonal skipped, as k_scatter) from word qoff[r] on, padded to a
+// whole quad, the first word flagged as the row's start.
+__global__ __launch_bounds__(kBlock) void k_scatter_quad(int64_t n, const int64_t* rp, const int32_t* col,
+                                                         const double* val, const int64_t* qoff, int32_t* qw,
+                                                         int fmt) {
+    int64_t lo, hi;
+    split_range(n, xcd_lid(), gridDim.x, lo, hi);
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+        const int64_t o = qoff[r];
+        int64_t d = 0;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int32_t j = col[e];
+            if ((int64_t)j == r) continue;
+            int32_t w = j;
+            if (fmt == FMT_SGN && val[e] < 0.0) w = (int32_t)((uint32_t)w | 0x80000000u);
+            if (d == 0) w |= kQStart;
+            qw[o + d] = w;
+            ++d;
+        }
+        const int64_t end = 4 * ((d > 0) ? (d + 3) / 4 : 1);
+        for (int64_t k = d; k < end; ++k) qw[o + k] = kQPad | (k == 0 ? kQStart : 0);
+    }
+}
+
+// Build the quad-chunk layout when the matrix qualifies (column words only,
+// every row at most kQRowMax off-diagonal entries); cnt = off-diagonal
+// entries per row.  The word offsets go through the basis area, unused yet.
+template <typename T>
+scg_status build_quad_chunks(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, const double* val,
+                             const std::vector<int32_t>& cnt) {
+    c->nqc = 0;
+    const int64_t n = c->n;
+    if (!c->qw || c->fmt == FMT_VAL) return SCG_OK;
+    for (int64_t r = 0; r < n; ++r)
+        if (cnt[r] > kQRowMax) return SCG_OK;
+    std::vector<int64_t> qoff(n);
+    std::vector<int2> qc;
+    int fill = 64;
+    for (int64_t r = 0; r < n; ++r) {
+        const int rq = std::max(1, (cnt[r] + 3) / 4);
+        if (fill + rq > 64) {
+            qc.push_back(make_int2((int)r, 0));
+            fill = 0;
+        }
+        qoff[r] = (int64_t)(qc.size() - 1) * 256 + 4 * fill;
+        fill += rq;
+        qc.back().y = fill;
+    }
+    if ((int64_t)qc.size() > c->qc_cap) return SCG_OK;   // cannot happen within the reserved bound
+    int64_t* dqoff = reinterpret_cast<int64_t*>(c->V);
+    HIP_TRY(hipMemcpyAsync(dqoff, qoff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->qc, qc.data(), sizeof(int2) * qc.size(), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_scatter_quad, dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, dqoff, c->qw,
+                       c->fmt);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->nqc = (int64_t)qc.size();
+    return SCG_OK;
+}
+
+// Shift, start vector, the first product and the first update of iteration
+// `it` (its partial sums are what the timed step-1 products reduce).
+template <typename T>
+void time_spmv_setup(scg_ctx* c, const IterArgs& it) {
+    enqueue_prep<T>(c, it);
+    launch_spmv<T, SPMV_LANCZOS>(c, basis_col<T>(c, 0), 0);
+    hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, prob<T>(c), 0, 1, 0);
+}
+
+// Autotuner: time the Lanczos SpMV on this matrix for each lanes-per-row
+// choice, column-segment count and grid, and the quad-chunk product when the
+// matrix has that layout, and keep the fastest.  The candidates run the
+// product of Lanczos step 1 of iteration 1 (after its shift, start vector,
+// first product and update), timed with HIP events on the context stream.
 template <typename T>
 scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, const double* val) {
     const IterArgs it = iter_args(c, 1);
-    enqueue_prep<T>(c, it);
+    time_spmv_setup<T>(c, it);   // candidates are timed as the step-1 product a solve repeats
+    const T* x1 = basis_col<T>(c, 1);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -584,9 +681,9 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
             for (int l : {2, 4, 8, 16, 32}) {
                 if (c->prm.spmv_lanes > 0 && l != c->prm.spmv_lanes) continue;
                 if (c->prm.spmv_lanes == 0 && l > 4 * mean + 4) break;
-                launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);   // warm-up
+                launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, l);   // warm-up
                 HIP_TRY(hipEventRecord(e0, c->stream));
-                for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, (const T*)c->V, 0, l);
+                for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, l);
                 HIP_TRY(hipEventRecord(e1, c->stream));
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -596,13 +693,31 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         }
         c->Gs = g_nat;
     }
+    // the quad-chunk product, when the matrix has that layout
+    if (c->nqc > 0 && (c->prm.spmv_lanes == 0 || c->prm.spmv_lanes == 1) && c->prm.segments <= 1) {
+        const int g_keep = c->Gs;
+        for (int g : {1536, 2048}) {
+            if (c->prm.spmv_grid > 0 && g != 1536) continue;   // a forced grid is applied afterwards
+            c->Gs = g;
+            launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, 1);   // warm-up
+            HIP_TRY(hipEventRecord(e0, c->stream));
+            for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, 1);
+            HIP_TRY(hipEventRecord(e1, c->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_l = 1; best_s = 1; best_g = g; }
+        }
+        c->Gs = g_keep;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (c->nseg != best_s) {
         scg_status st = build_segments<T>(c, best_s, row_ptr, col, val);
         if (st != SCG_OK) return st;
     }
-    if (best_g != 0) c->Gs = std::min(c->Gs, best_g);
+    if (best_l == 1) c->Gs = best_g;
+    else if (best_g != 0) c->Gs = std::min(c->Gs, best_g);
     c->lanes = best_l;
     return SCG_OK;
 }
@@ -684,6 +799,10 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     hipLaunchKernelGGL((k_scatter<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, b, c->rp,
                        c->col, (T*)c->val, dCraw, c->dC, c->b, inv_cF, inv_alpha, c->fmt);
     HIP_TRY(hipGetLastError());
+    {
+        scg_status st = build_quad_chunks<T>(c, row_ptr, col, val, hcnt);
+        if (st != SCG_OK) return st;
+    }
     if (c->lo) {   // K = {b} until sketchycgal_set_constraints
         HIP_TRY(hipMemcpyAsync(c->lo, c->b, 8 * n, hipMemcpyDeviceToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(c->hi, c->b, 8 * n, hipMemcpyDeviceToDevice, c->stream));
@@ -713,7 +832,8 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
         scg_status st = build_segments<T>(c, c->prm.segments, row_ptr, col, val);
         if (st != SCG_OK) return st;
     }
-    // forced SpMV shape (overrides the autotuner)
+    // forced SpMV shape (overrides the autotuner); the quad-chunk product needs its layout
+    if (c->prm.spmv_lanes == 1 && c->nqc == 0) return SCG_EINVAL;
     if (c->prm.spmv_lanes > 0) c->lanes = c->prm.spmv_lanes;
     if (c->prm.spmv_grid > 0) c->Gs = std::min(c->Gs, std::max(8, round8(c->prm.spmv_grid)));
     HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * c->prm.T, c->stream));
@@ -733,7 +853,8 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (p->precision != SCG_FP64 && p->precision != SCG_FP32_STREAM) return false;
     if (qmax_for(*p, n) + 1 > kQCap) return false;
     const int l = p->spmv_lanes;
-    if (l != 0 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
+    if (l != 0 && l != 1 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
+    if (l == 1 && (p->segments > 1 || p->matrix_format == 1)) return false;   // the quad-chunk product
     if (p->spmv_grid < 0 || p->spmv_grid > kGMax) return false;
     if (p->basis_mode != 0 && p->basis_mode != 1) return false;
     if (p->basis_mode == 1 && p->reorth == 2) return false;   // full reorthogonalisation needs the stored basis
@@ -826,6 +947,10 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->logs = (scg_iter_log*)(base + L.logs);
     c->recon = (double*)(base + L.recon);
     c->recon_bytes = L.recon_bytes;
+    c->qc_cap = quad_chunk_cap(*p, n, nnz);
+    c->qw = (c->qc_cap > 0) ? (int32_t*)(base + L.qw) : nullptr;
+    c->qc = (c->qc_cap > 0) ? (int2*)(base + L.qc) : nullptr;
+    c->nqc = 0;
     scg_status st = (p->precision == SCG_FP32_STREAM) ? init_typed<float>(c, row_ptr, col, val, b, omega)
                                                        : init_typed<double>(c, row_ptr, col, val, b, omega);
     if (st != SCG_OK) {
@@ -996,12 +1121,12 @@ scg_status sketchycgal_time_spmv(scg_ctx* c, int32_t reps, double* avg_ms) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    if (c->prm.precision == SCG_FP32_STREAM) enqueue_prep<float>(c, it);
-    else enqueue_prep<double>(c, it);
+    if (c->prm.precision == SCG_FP32_STREAM) time_spmv_setup<float>(c, it);
+    else time_spmv_setup<double>(c, it);
     HIP_TRY(hipEventRecord(e0, c->stream));
     for (int r = 0; r < reps; ++r) {
-        if (c->prm.precision == SCG_FP32_STREAM) launch_spmv<float, SPMV_LANCZOS>(c, (const float*)c->V, 0);
-        else launch_spmv<double, SPMV_LANCZOS>(c, (const double*)c->V, 0);
+        if (c->prm.precision == SCG_FP32_STREAM) launch_spmv<float, SPMV_LANCZOS>(c, basis_col<float>(c, 1), 1);
+        else launch_spmv<double, SPMV_LANCZOS>(c, basis_col<double>(c, 1), 1);
     }
     HIP_TRY(hipEventRecord(e1, c->stream));
     HIP_TRY(hipEventSynchronize(e1));

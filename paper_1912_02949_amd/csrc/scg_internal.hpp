@@ -72,6 +72,9 @@ struct Prob {
     T* S;                 // sketch, n x R column-major (column c at c*ld)
     const int32_t* rb;    // row-block boundaries, int32[nrb+1]
     int nrb;
+    const int32_t* qw;    // quad-chunk layout: column words, 64 quads per chunk
+    const int2* qc;       // per chunk: (first row, quads used)
+    int64_t nqc;          // chunks
     DevScalars* sc;
     // per-workgroup partial sums, one buffer per producing kernel
     double* p_prep;       // k_prep,        G  x 6
@@ -106,7 +109,7 @@ struct scg_ctx {
     int qmax;
     int G;          // workgroups for vector kernels
     int Gs;         // workgroups for SpMV kernels
-    int lanes;      // lanes per row in the SpMV row reduction
+    int lanes;      // lanes per row in the SpMV row reduction; 1: the quad-chunk product
     int nseg;       // column segments (1, 2 or 4): launch s gathers only x[s*seglen, (s+1)*seglen)
     int64_t seglen;
     int32_t* rp_seg[scg::kSegMax];   // per segment: row pointers into col/val (absolute)
@@ -144,6 +147,10 @@ struct scg_ctx {
     double* lo;      // box constraint set, scaled (constraint_set = 1), else null
     double* hi;
     size_t recon_bytes;
+    int32_t* qw;     // quad-chunk layout of the off-diagonal columns (null when not reserved)
+    int2* qc;        // per chunk: (first row, quads used)
+    int64_t nqc;     // chunks built (0: the matrix does not qualify)
+    int64_t qc_cap;  // chunks reserved
 };
 
 // Arguments of the FP64 Nystrom reconstruction of one sketch (column-major

@@ -204,6 +204,54 @@ struct SegArgs {
     int last;
 };
 
+// Scale of the vector being multiplied, shared by both product kernels.
+// LANCZOS (last column segment): step 0 takes 1/||v_0|| from k_prep's partials
+// (and records the state dot products), step i > 0 takes rho_{i-1} from the
+// update's partials and applies the breakdown test (false: the recurrence
+// has ended, the caller returns).  OBJ: 1/||v|| of the Ritz vector.
+template <int MODE, typename T>
+__device__ __forceinline__ bool spmv_scale(const Prob<T>& P, int step, bool last, double& xs) {
+    DevScalars* sc = P.sc;
+    xs = 1.0;
+    if (MODE == SPMV_OBJ) xs = sc->inv_vnorm;
+    if (MODE == SPMV_LANCZOS && last) {
+        if (step == 0) {
+            double tot[kWPrep];
+            reduce_partials<kWPrep>(P.p_prep, P.G, tot);
+            xs = 1.0 / sqrt(tot[0]);
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sc->inv[0] = xs;
+                sc->d_yb = tot[1];
+                sc->d_zz = tot[2];
+                sc->d_gapdot = tot[3];
+                sc->d_zb2 = tot[4];
+                sc->b2 = tot[5];
+                sc->k = 0;
+                if (!isfinite(xs)) sc->flags |= 2;
+            }
+        } else {
+            double tot[kWUpd];
+            reduce_partials<kWUpd>(P.p_upd, P.G, tot);
+            const double rho = sqrt(tot[0]);
+            const double om = sc->omega[step - 1];
+            const double rp = (step > 1) ? sc->rho[step - 2] : 0.0;
+            if (lanczos_breakdown(rho, om, rp)) {
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    sc->done = 1;
+                    sc->flags |= isfinite(rho) ? 1 : 3;
+                }
+                return false;
+            }
+            xs = 1.0 / rho;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sc->rho[step - 1] = rho;
+                sc->inv[step] = xs;
+            }
+        }
+    }
+    return true;
+}
+
 template <typename T, int LANES, int MODE, int RB, int FMT>
 __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict__ x, int step, SegArgs sg) {
     __shared__ T stage_all[kWaves][kNB + 4];
@@ -231,42 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
         if (!(dB.x - dA.x == 1 && dB.y - dA.y > kNB)) fetch_block<T, FMT>(P, dA.y, dB.y, lane, cur);
     }
     double xs = 1.0;
-    if (MODE == SPMV_OBJ) xs = sc->inv_vnorm;
-    if (MODE == SPMV_LANCZOS && sg.last) {
-        if (step == 0) {
-            double tot[kWPrep];
-            reduce_partials<kWPrep>(P.p_prep, P.G, tot);
-            xs = 1.0 / sqrt(tot[0]);
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                sc->inv[0] = xs;
-                sc->d_yb = tot[1];
-                sc->d_zz = tot[2];
-                sc->d_gapdot = tot[3];
-                sc->d_zb2 = tot[4];
-                sc->b2 = tot[5];
-                sc->k = 0;
-                if (!isfinite(xs)) sc->flags |= 2;
-            }
-        } else {
-            double tot[kWUpd];
-            reduce_partials<kWUpd>(P.p_upd, P.G, tot);
-            const double rho = sqrt(tot[0]);
-            const double om = sc->omega[step - 1];
-            const double rp = (step > 1) ? sc->rho[step - 2] : 0.0;
-            if (lanczos_breakdown(rho, om, rp)) {
-                if (blockIdx.x == 0 && threadIdx.x == 0) {
-                    sc->done = 1;
-                    sc->flags |= isfinite(rho) ? 1 : 3;
-                }
-                return;
-            }
-            xs = 1.0 / rho;
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                sc->rho[step - 1] = rho;
-                sc->inv[step] = xs;
-            }
-        }
-    }
+    if (!spmv_scale<MODE>(P, step, sg.last, xs)) return;
     const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
     double acc0 = 0.0, acc1 = 0.0;
     const double cv = (FMT == FMT_VAL) ? 1.0 : P.cval;
@@ -357,6 +370,108 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
         dC = dD;
     }
     if (MODE == SPMV_APPLY || !sg.last) return;
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    if (lane == 0) {
+        wred[wv][0] = acc0;
+        wred[wv][1] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i < kWaves; ++i) {
+            s0 += wred[i][0];
+            s1 += wred[i][1];
+        }
+        if (MODE == SPMV_LANCZOS) {
+            P.p_spmv[blockIdx.x] = s0;
+        } else {
+            P.p_obj[(size_t)blockIdx.x * 2 + 0] = s0;
+            P.p_obj[(size_t)blockIdx.x * 2 + 1] = s1;
+        }
+    }
+}
+
+// The same product over the quad-chunk layout (matrices whose off-diagonal
+// values share one magnitude and whose rows hold at most kQRowMax entries).
+// Each row's column words are padded to whole 16-byte quads and rows are
+// packed, whole, into chunks of 64 quads; P.qc[c] = (first row, quads used).
+// Word bits: 31 sign (FMT_SGN), 30 first quad of a row, 29 padding entry,
+// 28..0 column.  One wave takes one chunk at a time, one quad per lane: a
+// lane's row is the chunk's first row plus the count of row starts at or
+// before it (ballot), rows are summed by a segmented scan across the lanes,
+// and the row's last lane applies the shift and the scale exactly as k_spmv
+// does.  There is no LDS staging and no row-pointer stream, and every lane's
+// gathers depend on one load only.
+constexpr int kQStart = 1 << 30, kQPad = 1 << 29, kQColMask = (1 << 29) - 1;
+constexpr int kQRowMax = 128;   // off-diagonal entries of the longest row the layout takes
+
+template <typename T, int FMT>
+__device__ __forceinline__ T quad_term(const T* __restrict__ x, int w) {
+    const T xv = (w & kQPad) ? (T)0 : x[w & kQColMask];
+    return (FMT == FMT_SGN && w < 0) ? -xv : xv;
+}
+
+template <typename T, int MODE, int FMT>
+__global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict__ x, int step) {
+    __shared__ double wred[kWaves][2];
+    DevScalars* sc = P.sc;
+    if (MODE == SPMV_LANCZOS && sc->done) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t clo, chi;
+    split_range(P.nqc, xcd_lid() * kWaves + wv, gridDim.x * kWaves, clo, chi);
+    int2 cd = make_int2(0, 0);
+    i32x4_t w = {kQPad, kQPad, kQPad, kQPad};
+    if (clo < chi) {
+        cd = P.qc[clo];
+        if (lane < cd.y) w = reinterpret_cast<const i32x4_t*>(P.qw)[(size_t)clo * 64 + lane];
+    }
+    double xs;
+    if (!spmv_scale<MODE>(P, step, true, xs)) return;
+    const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
+    const double cv = P.cval;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t c = clo; c < chi; ++c) {
+        const bool valid = lane < cd.y;
+        const bool start = valid && (w.x & kQStart);
+        const unsigned long long bal = __ballot(start);
+        const int rid = __popcll(bal & ((2ull << lane) - 1ull)) - 1;
+        T a = valid ? (quad_term<T, FMT>(x, w.x) + quad_term<T, FMT>(x, w.y)) +
+                          (quad_term<T, FMT>(x, w.z) + quad_term<T, FMT>(x, w.w))
+                    : (T)0;
+        const int r0 = cd.x, nq = cd.y;
+        if (c + 1 < chi) {
+            cd = P.qc[c + 1];
+            w = (lane < cd.y) ? reinterpret_cast<const i32x4_t*>(P.qw)[(size_t)(c + 1) * 64 + lane]
+                              : i32x4_t{kQPad, kQPad, kQPad, kQPad};
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T ya = __shfl_up(a, off, 64);
+            const int yr = __shfl_up(rid, off, 64);
+            if (lane >= off && yr == rid) a += ya;
+        }
+        const bool next_start = (lane == 63) || ((bal >> (lane + 1)) & 1ull);
+        if (valid && (lane == nq - 1 || next_start)) {
+            const int r = r0 + rid;
+            const double xr = (double)x[r], sr = (double)P.s[r];
+            const double off = (double)a * cv;
+            if (MODE == SPMV_LANCZOS) {
+                const T ut = (T)((off + sr * xr) * xs);
+                P.u[r] = ut;
+                acc0 += xr * xs * (double)ut;
+            } else if (MODE == SPMV_OBJ) {
+                const double cvr = (off + P.dC[r] * xr) * xs;
+                const double dvr = (off + sr * xr) * xs;
+                acc0 += xr * xs * cvr;
+                const double rr = dvr - xi * xr * xs;
+                acc1 += rr * rr;
+            } else {
+                P.u[r] = (T)(off + sr * xr);
+            }
+        }
+    }
+    if (MODE == SPMV_APPLY) return;
     acc0 = wave_sum(acc0);
     acc1 = wave_sum(acc1);
     if (lane == 0) {

@@ -55,7 +55,7 @@ def test_workspace_size_and_validation():
     assert st2 == _lib.SCG_OK and b2 < b
     bad = [dict(R=0), dict(R=33), dict(n=5, R=6), dict(T=0), dict(beta0=0.0), dict(beta0=-1.0), dict(K=-1.0),
            dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=3), dict(reorth=-1), dict(precision=7), dict(n=0),
-           dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_grid=-1), dict(spmv_grid=4096),
+           dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_lanes=1, segments=2), dict(spmv_lanes=1, matrix_format=1), dict(spmv_grid=-1), dict(spmv_grid=4096),
            dict(q_mode=1, q_fixed=600, n=10_000), dict(basis_mode=2), dict(basis_mode=-1), dict(omega_mode=2),
            dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=3), dict(constraint_set=-1)]
     for kw in bad:
@@ -88,6 +88,21 @@ def test_storage_optimal_modes_shrink_the_workspace():
     _, c4 = _ws(n=n2, nnz=5 * n2, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=120)
     _, d3 = _ws(n=n, nnz=5 * n, R=R, T=T, basis_mode=1, omega_mode=1, q_mode=1, q_fixed=44)
     assert abs((c4 - c3) - (b4 - d3)) <= slack
+
+
+def test_quad_chunk_layout_reservation():
+    # column words for chunks of 64 quads, each row padded to whole quads: at
+    # most nnz/4 + n quads, every chunk but the last holding at least 33 of
+    # them; not reserved when a row-block product or stored values are forced
+    n, nnz = 1_000_000, 9_000_000
+    st0, b_auto = _ws(n=n, nnz=nnz)
+    st1, b_rows = _ws(n=n, nnz=nnz, spmv_lanes=2)
+    st2, b_vals = _ws(n=n, nnz=nnz, matrix_format=1)
+    st3, b_quad = _ws(n=n, nnz=nnz, spmv_lanes=1)
+    assert st0 == st1 == st2 == st3 == _lib.SCG_OK
+    chunks = (nnz // 4 + n + 1) // 33 + 2
+    assert b_rows == b_vals and b_quad == b_auto
+    assert 0 <= (b_auto - b_rows) - (256 * 4 * chunks + 8 * chunks) <= 2 * 256
 
 
 def test_box_constraint_set_adds_two_vectors():

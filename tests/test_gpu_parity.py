@@ -69,7 +69,7 @@ def test_apply_matches_operator(which, precision, tol, matrix_format, cfg1):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
-@pytest.mark.parametrize("lanes,grid", [(2, 16), (4, 8), (8, 0), (32, 24)])
+@pytest.mark.parametrize("lanes,grid", [(2, 16), (4, 8), (8, 0), (32, 24), (1, 0), (1, 16)])
 def test_apply_with_forced_spmv_shape(lanes, grid, precision, tol):
     """Fewer workgroups than row-block ranges (each wave walks several blocks)
     and every lane count give the same product."""
