@@ -422,9 +422,14 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
     split_range(P.nqc, xcd_lid() * kWaves + wv, gridDim.x * kWaves, clo, chi);
     int2 cd = make_int2(0, 0);
     i32x4_t w = {kQPad, kQPad, kQPad, kQPad};
+    T tf[4] = {(T)0, (T)0, (T)0, (T)0};
     if (clo < chi) {
         cd = P.qc[clo];
         if (lane < cd.y) w = reinterpret_cast<const i32x4_t*>(P.qw)[(size_t)clo * 64 + lane];
+        tf[0] = quad_term<T, FMT>(x, w.x);
+        tf[1] = quad_term<T, FMT>(x, w.y);
+        tf[2] = quad_term<T, FMT>(x, w.z);
+        tf[3] = quad_term<T, FMT>(x, w.w);
     }
     double xs;
     if (!spmv_scale<MODE>(P, step, true, xs)) return;
@@ -436,9 +441,11 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
         const bool start = valid && (w.x & kQStart);
         const unsigned long long bal = __ballot(start);
         const int rid = __popcll(bal & ((2ull << lane) - 1ull)) - 1;
-        T a = valid ? (quad_term<T, FMT>(x, w.x) + quad_term<T, FMT>(x, w.y)) +
-                          (quad_term<T, FMT>(x, w.z) + quad_term<T, FMT>(x, w.w))
-                    : (T)0;
+        T a;
+        if (c == clo) a = valid ? (tf[0] + tf[1]) + (tf[2] + tf[3]) : (T)0;
+        else a = valid ? (quad_term<T, FMT>(x, w.x) + quad_term<T, FMT>(x, w.y)) +
+                             (quad_term<T, FMT>(x, w.z) + quad_term<T, FMT>(x, w.w))
+                       : (T)0;
         const int r0 = cd.x, nq = cd.y;
         if (c + 1 < chi) {
             cd = P.qc[c + 1];
