@@ -387,7 +387,9 @@ def main():
             summ = sp.summary()
             sp.close()
             shapes.append({"lanes": lanes, "workgroups": summ["spmv_grid"], "segments": summ["spmv_segments"],
-                           "spmv_avg_us": ms.value * 1e3, "lanczos_launches_before_timing": sum(pqs[:2])})
+                           "spmv_avg_us": ms.value * 1e3,
+                           # two iterations' Lanczos products, then the step-0 product time_spmv forms first
+                           "lanczos_launches_before_timing": sum(pqs[:2]) + 1})
             progress(f"probe lanes={lanes} workgroups={summ['spmv_grid']} segments={seg}: {ms.value * 1e3:.1f} us")
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
