@@ -30,12 +30,30 @@ __device__ __forceinline__ double rcp_refined(double q) {
 
 // Number of eigenvalues of tridiag(e, d, e) (size k) smaller than x: the
 // number of negative pivots of the LDL^T factorisation of T - x I.
+// The entries of each block of eight steps are read before the block's
+// recurrence runs, so the LDS latency is paid once per block instead of once
+// per step; the arithmetic and its order are those of the plain loop.
 __device__ inline int sturm_count(const double* d, const double* e2, int k, double x, double pivmin) {
     int cnt = 0;
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += (q < 0.0);
-    for (int i = 1; i < k; ++i) {
+    int i = 1;
+    for (; i + 8 <= k; i += 8) {
+        double dd[8], ee[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            dd[j] = d[i + j];
+            ee[j] = e2[i + j - 1];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            q = (dd[j] - x) - ee[j] * rcp_refined(q);
+            if (fabs(q) < pivmin) q = -pivmin;
+            cnt += (q < 0.0);
+        }
+    }
+    for (; i < k; ++i) {
         q = (d[i] - x) - e2[i - 1] * rcp_refined(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += (q < 0.0);
