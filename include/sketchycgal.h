@@ -141,7 +141,8 @@ typedef struct {
     double objective;         /* <C, X>                                     */
     double infeasibility;     /* ||diag X - b|| (box or ball: dist_K)       */
     double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
-    int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction               */
+    int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction (1: the
+                                 quad-chunk product)                                            */
     int32_t spmv_segments;    /* column segments of the SpMV                                   */
     int32_t matrix_format;    /* storage of the off-diagonal values: 0 values, 1 columns only
                                  (common value), 2 columns with sign bit (common magnitude)  */

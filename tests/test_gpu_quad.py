@@ -29,10 +29,22 @@ def _with_isolated(g: synth.Graph, extra: int) -> synth.Graph:
     return synth.Graph(n=g.n + extra, src=g.src, dst=g.dst, w=g.w)
 
 
+def _circulant(n: int, half_degree: int) -> synth.Graph:
+    # vertex i joined to i +- 1 .. i +- half_degree (mod n): every row holds 2 half_degree entries
+    src = np.repeat(np.arange(n, dtype=np.int64), half_degree)
+    dst = (src + np.tile(np.arange(1, half_degree + 1, dtype=np.int64), n)) % n
+    lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+    return synth.Graph(n=n, src=lo, dst=hi, w=np.ones(lo.size))
+
+
 CASES = {
     "cfg1": lambda: synth.config_instance(1),
     "torus_pm1": lambda: synth.laplacian_instance(synth.torus_longrange(128, 91)),
     "isolated": lambda: synth.laplacian_instance(_with_isolated(synth.erdos_renyi(3000, 9000, 17), 77)),
+    # rows of 17 quads: three rows per chunk, 13 quads of every chunk unused
+    "circulant68": lambda: synth.laplacian_instance(_circulant(1000, 34)),
+    # rows at the layout's limit of 128 entries: two rows fill a chunk
+    "circulant128": lambda: synth.laplacian_instance(_circulant(700, 64)),
 }
 
 
@@ -44,6 +56,8 @@ def _operator_ref(inst, x):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
 @pytest.mark.parametrize("which", list(CASES))
 def test_quad_product_matches_operator(which, precision, tol):
+    # rows of up to 128 entries summed in FP32: the bar for that precision is
+    # the one every product test uses (2e-6 relative to the largest entry)
     need_gpu()
     inst = CASES[which]()
     announce(f"quad product {which} n={inst.n} {precision}")
