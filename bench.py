@@ -13,6 +13,10 @@ Also reported:
                 ||diag X - b|| first reaches the FP64 solve's final value
                 (speedup at equal final infeasibility)
   spmv_other_workloads  the Lanczos SpMV alone on workloads 5 and 3 (roofline context)
+  workload_1    the 800-vertex G(n, m) workload as its text specifies it (FP64,
+                q = 36, R = 10, T = 500): iterations/s of the single engine and
+                of the batched engine running it as a one-instance batch
+                (launch- and latency-bound; no roofline)
   batched       the batched form: 256 Erdos-Renyi instances (average degree 8,
                 n uniform in [200, 20000]), R = 8, T = 1000, all advanced by one
                 launch per iteration; instance-iterations per second, FP32 and FP64
@@ -256,6 +260,34 @@ def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10):
     return rate
 
 
+def workload1_leg(torch) -> dict:
+    """Workload 1 (n = 800, 19 176 unit edges, FP64, q = 36, R = 10, T = 500): T iterations timed
+    after initialisation, once per engine, the first run of each untimed."""
+    import synth
+    from paper_1912_02949_amd import BatchedSketchyCGAL, Params, SketchyCGAL
+    inst = synth.config_instance(1)
+    prm = Params(R=10, T=500, seed=synth.CONFIG_SEEDS[1], q_mode=1, q_fixed=36, precision="fp64")
+    out = {"workload": "G(n, m), n = 800, m = 19176, unit weights, R = 10, T = 500, q = 36, FP64"}
+    makers = {"single_engine": lambda: SketchyCGAL(inst.row_ptr, inst.col, inst.val, inst.b, prm),
+              "batched_engine_one_instance": lambda: BatchedSketchyCGAL([inst], prm)}
+    for name, make in makers.items():
+        best, obj = None, None
+        for rep in range(2):
+            s = make()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            obj = s.summary()["objective"] if name == "single_engine" else s.summary(0)["objective"]
+            if rep == 1:
+                best = dt
+            del s
+        out[name] = {"iters_per_s": prm.T / best, "ms_per_iteration": 1e3 * best / prm.T,
+                     "sdp_value": -obj}
+    return out
+
+
 def spmv_line(torch, k: int, precision: str):
     """Lanczos SpMV of workload k alone: autotuned shape, 50 back-to-back launches (HIP events)."""
     import synth
@@ -488,6 +520,10 @@ def main():
             others[f"workload_{k}"] = {"graph": name,
                                        **{prec: spmv_line(torch, k, prec) for prec in ("fp32", "fp64")}}
             progress(f"SpMV line for workload {k} done")
+        w1 = workload1_leg(torch)
+        progress("workload 1 done")
+    else:
+        w1 = None
     cpu = None if args.no_cpu else cpu_baseline(inst, T, args.cpu_seconds)
 
     value = args.steps * T / dt32
@@ -549,6 +585,7 @@ def main():
         "storage_optimal_fp32": storage,
         "batched": batched,
         "spmv_other_workloads": others,
+        "workload_1": w1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
