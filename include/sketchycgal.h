@@ -80,7 +80,10 @@ typedef struct {
     int32_t  matrix_format; /* 0: compress the off-diagonal values when they share one
                                magnitude (columns only, sign in bit 31); 1: always store values */
     int32_t  autotune;      /* 1: time the SpMV variants (lanes per row, column segments, grid
-                               size) at init and keep the fastest                             */
+                               size, and the quad-chunk product when the matrix qualifies) at
+                               init on the product of Lanczos step 1, and keep the fastest;
+                               runs when the matrix has at least 2^20 off-diagonal entries or
+                               segments is set                                                */
     int32_t  segments;      /* column segments of the SpMV: 0 = chosen by the autotuner
                                (1 below 1M nonzeros), or 1, 2, 4                              */
     int32_t  spmv_lanes;    /* lanes per row of the SpMV reduction: 0 = autotuned / by mean
