@@ -229,6 +229,28 @@ scg_status sketchycgal_reconstruct(scg_ctx* ctx, double* U, double* lambda, doub
  * precision when they are stored).  Synchronises. */
 scg_status sketchycgal_round(scg_ctx* ctx, const double* U, int8_t* chi, double* weights, int32_t* best);
 
+/* MaxCut rounding for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid hipMalloc): the cut
+ * weights of sketchycgal_round computed from the caller's matrix with no
+ * context and no workspace.  The partial sums live in a static device array of
+ * 1024 x 33 doubles (264 KiB) that the library keeps on every device it has
+ * run this call on until the process ends; nothing in it needs clearing.
+ *   n, nnz   sizes of C (n >= 1, nnz >= 0)
+ *   row_ptr  device int64[n+1], col device int32[nnz], val device double[nnz]:
+ *            C in CSR with its diagonal, as for sketchycgal_init; a row pointer
+ *            or column outside its range is reported, never followed
+ *   R        columns of U, 1 <= R <= min(n, 32)
+ *   U        device double[n*R] column-major (as sketchycgal_reconstruct writes)
+ *   chi      device int8[n]: the heaviest cut, or NULL
+ *   weights  host double[R]: -chi_j^T C chi_j for every column (C as given, FP64)
+ *   best     host int32: index of the heaviest (lowest index on ties)
+ *   stream   hipStream_t (NULL = default stream) on the current device
+ * Synchronises the stream.  SCG_EINVAL for bad sizes or pointers and for a
+ * malformed CSR.  Calls that overlap on one device share the array and race:
+ * issue them one at a time per device. */
+scg_status scg_round_csr(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t R, const double* U, int8_t* chi, double* weights, int32_t* best, void* stream);
+
 /* Copy up to `max` iteration records into host memory (synchronises). */
 scg_status sketchycgal_log(scg_ctx* ctx, scg_iter_log* host_out, int32_t max, int32_t* count);
 

@@ -50,6 +50,7 @@ EXPORTS = [
     "scg_batch_workspace_size", "sketchycgal_batch_init", "sketchycgal_batch_step", "sketchycgal_batch_log",
     "sketchycgal_batch_summary", "sketchycgal_batch_get_state", "sketchycgal_batch_set_state", "sketchycgal_batch_reconstruct",
     "sketchycgal_batch_destroy", "sketchycgal_batch_round", "sketchycgal_batch_set_beta0",
+    "scg_round_csr",
 ]
 
 _lib = None
@@ -94,6 +95,7 @@ def load() -> C.CDLL:
     lib.sketchycgal_set_constraints.argtypes = [vp, vp, vp]
     lib.sketchycgal_set_ball.argtypes = [vp, C.c_double]
     lib.sketchycgal_batch_round.argtypes = [vp, i32, vp, vp, P(C.c_double), P(i32)]
+    lib.scg_round_csr.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, P(C.c_double), P(i32), vp]
     lib.sketchycgal_batch_destroy.argtypes = [vp]
     lib.sketchycgal_batch_destroy.restype = None
     lib.scg_status_string.argtypes = [C.c_int]
