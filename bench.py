@@ -1,33 +1,38 @@
 """Benchmark: SketchyCGAL MaxCut solves per second on one MI355X.
 
-Workload: MaxCut SDP on a 1024 x 1024 torus (4-neighbour) plus 2n random
-long-range edges, weights +-1 (n = 1,048,576), sketch size R = 10,
-T = 2000 iterations, the paper's Lanczos schedule q_t = ceil(t^(1/4) ln n).
-One step = one whole solve on inputs resident in HBM: initialisation
-(validation, scaling, diagonal split, Omega), T iterations, and the Nystrom
-reconstruction.  `value` is CGAL iterations per second of the FP32-stream
-form; the plain-FP64 form is timed beside it.
+Headline workload: MaxCut SDP on a 1024 x 1024 torus (4-neighbour) plus 2n
+random long-range edges, weights +-1 (n = 1,048,576), sketch size R = 10,
+T = 2000 iterations, the paper's Lanczos schedule q_t = ceil(t^(1/4) ln n),
+plain FP64 (the paper's precision).  One step = one whole solve on inputs
+resident in HBM: initialisation (validation, scaling, diagonal split, Omega,
+SpMV autotuning), T iterations, and the Nystrom reconstruction.  `value` is
+CGAL iterations per second of that solve.
 
 Also reported:
-  fp64_plain    the plain-FP64 solve, and the FP32 solve stopped where its
-                ||diag X - b|| first reaches the FP64 solve's final value
-                (speedup at equal final infeasibility)
-  spmv_other_workloads  the Lanczos SpMV alone on workloads 5 and 3 (roofline context)
+  result_fp64   the FP64 solve's result and Lanczos SpMV line, and how far the
+                same solve with its products summed in another order ends up
+                (whole runs of this method follow rounding)
+  fp32_stream   the FP32-stream/FP64-critical form of the same workload: one
+                solve, its difference from FP64, the speedup at equal final
+                ||diag X - b||, MaxCut rounding of its reconstruction, its SpMV
+  other_workloads  whole FP32-stream solves of the 2^23-vertex random geometric
+                workload (T = 500) and the 2^22-vertex power-law workload
+                (T = 1000), with their Lanczos SpMV lines
   workload_1    the 800-vertex G(n, m) workload as its text specifies it (FP64,
                 q = 36, R = 10, T = 500): iterations/s of the single engine and
                 of the batched engine running it as a one-instance batch
-                (launch- and latency-bound; no roofline)
-  batched       the batched form: 256 Erdos-Renyi instances (average degree 8,
-                n uniform in [200, 20000]), R = 8, T = 1000, all advanced by one
-                launch per iteration; instance-iterations per second, FP32 and FP64
-  roofline      the Lanczos SpMV kernel: algorithmic bytes per launch over its
-                average duration (HIP events on the solver's stream) against
-                the MI355X HBM peak; `traffic` is the rocprofv3-measured HBM
-                bytes per launch of the shape the autotuner chose (lanes per
-                row, workgroups), from the committed counter summary when it
-                matches the current kernel source, else null
-  cpu_baseline  the FP64 oracle on this host's cores, on a bounded sample of
-                the same workload, extrapolated over the whole Lanczos schedule
+  batched       256 Erdos-Renyi instances (average degree 8, n uniform in
+                [200, 20000]), R = 8, T = 1000, all advanced by one launch per
+                iteration; FP32 and FP64
+  roofline      the Lanczos SpMV of the geometric workload (its working set
+                exceeds the 256 MB last-level cache): algorithmic bytes per
+                product (values + int32 columns, row pointers, x, shift, u) over
+                its average duration (HIP events on the solver's stream) against
+                the MI355X HBM peak; `traffic` is the rocprofv3-measured HBM bytes
+                per launch of the chosen shape from the committed counter summary
+                when it matches the current kernel source, else null
+  cpu_baseline  the FP64 oracle on this host, on a bounded sample of the
+                headline workload, extrapolated over the whole Lanczos schedule
 """
 from __future__ import annotations
 
@@ -213,6 +218,7 @@ def cpu_baseline(inst, T: int, seconds: float = 15.0):
         "value": T / full_time,
         "unit": "CGAL iters/s",
         "cores": 1,
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": (f"first {done_iters} of {T} iterations ({work_done} operator applications incl. the objective "
                    f"product) in {spent:.1f} s, FP64, scipy CSR products, one thread; extrapolated over the whole "
@@ -288,31 +294,6 @@ def workload1_leg(torch) -> dict:
     return out
 
 
-def spmv_line(torch, k: int, precision: str):
-    """Lanczos SpMV of workload k alone: autotuned shape, 50 back-to-back launches (HIP events)."""
-    import synth
-    from paper_1912_02949_amd import Params
-    inst = synth.config_instance(k)
-    sp = Solve(inst, Params(R=10, T=100, seed=synth.CONFIG_SEEDS[k], precision=precision), torch)
-    sp.init()
-    sp.lib.sketchycgal_step(sp.ctx, 2)
-    ms = C.c_double()
-    sp.lib.sketchycgal_time_spmv(sp.ctx, 50, C.byref(ms))
-    summ = sp.summary()
-    sp.close()
-    es = 4 if precision == "fp32" else 8
-    nnz_off = inst.nnz - inst.n
-    per_nz = 4 + (es if summ["matrix_format"] == 0 else 0)
-    by = per_nz * nnz_off + 4 * (inst.n + 1) + 3 * es * inst.n
-    gbs = by / (ms.value * 1e-3) / 1e9
-    return {"n": inst.n, "nnz_offdiag": nnz_off, "avg_launch_us": ms.value * 1e3, "algorithmic_bytes_per_launch": by,
-            "traffic": measured_traffic(k, summ) if precision == "fp32" else None,
-            "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "kernel": spmv_kernel_name(summ),
-            "lanes_per_row": summ["spmv_lanes"],
-            "column_segments": summ["spmv_segments"], "workgroups": summ["spmv_grid"],
-            "matrix_format": ["values", "columns only", "columns with sign bit"][summ["matrix_format"]]}
-
-
 def batched_bytes(n: int, m: int, k: int, es: int, cb: int, vb: int, R: int) -> int:
     """Bytes one batched iteration of a problem with n rows, m off-diagonal entries and k Lanczos steps
     streams through memory, each array counted once per pass as the kernel reads or writes it:
@@ -368,6 +349,64 @@ def batched_leg(torch, T: int, with_fp64: bool):
     return out
 
 
+def spmv_roofline(solve, inst, precision: str, reps: int, k: int) -> dict:
+    """The Lanczos SpMV of a solver context: `reps` back-to-back products of Lanczos step 1 on the solver's
+    stream, timed with HIP events; algorithmic bytes per product as the scope table counts them (values +
+    int32 columns, row pointers, x, shift, u written) and, beside them, the bytes the chosen storage format
+    needs (no value stream when the off-diagonal values share one magnitude)."""
+    ms = C.c_double()
+    from paper_1912_02949_amd._lib import check
+    check(solve.lib.sketchycgal_time_spmv(solve.ctx, reps, C.byref(ms)), "time_spmv")
+    summ = solve.summary()
+    es = 4 if precision == "fp32" else 8
+    n, nnz_off = inst.n, inst.nnz - inst.n
+    by = (4 + es) * nnz_off + 4 * (n + 1) + 3 * es * n
+    by_fmt = (4 + (es if summ["matrix_format"] == 0 else 0)) * nnz_off + 4 * (n + 1) + 3 * es * n
+    us = ms.value * 1e3
+    gbs = by / (us * 1e-6) / 1e9
+    return {"kernel": spmv_kernel_name(summ), "lanes_per_row": summ["spmv_lanes"],
+            "column_segments": summ["spmv_segments"], "workgroups": summ["spmv_grid"],
+            "matrix_format": ["values", "columns only", "columns with sign bit"][summ["matrix_format"]],
+            "avg_product_us": us, "launches_per_product": summ["spmv_segments"],
+            "algorithmic_bytes_per_product": by, "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "format_bytes_per_product": by_fmt, "format_GBps": by_fmt / (us * 1e-6) / 1e9,
+            "gathers_per_s": nnz_off / (us * 1e-6),
+            "traffic": measured_traffic(k, summ) if precision == "fp32" else None}
+
+
+def solve_leg(torch, k: int, inst, precision: str, T: int, spmv_reps: int = 100, warm_T: int = 20) -> dict:
+    """Whole solve of workload k (init, T iterations, reconstruction) timed once after a short warm-up
+    solve (T = warm_T) of the same problem; then its Lanczos SpMV line."""
+    import synth
+    from paper_1912_02949_amd import Params
+    warm = Solve(inst, Params(R=10, T=warm_T, seed=synth.CONFIG_SEEDS[k], precision=precision), torch)
+    warm.run()
+    del warm
+    sv = Solve(inst, Params(R=10, T=T, seed=synth.CONFIG_SEEDS[k], precision=precision), torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv.init()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    from paper_1912_02949_amd._lib import check
+    check(sv.lib.sketchycgal_step(sv.ctx, T), "step")
+    check(sv.lib.sketchycgal_reconstruct(sv.ctx, sv.U.data_ptr(), sv.lam.data_ptr(), sv.err.data_ptr()),
+          "reconstruct")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    summ = sv.summary()
+    last = sv.record()
+    norm_b = math.sqrt(float((inst.b * inst.b).sum()))
+    out = {"precision": precision, "T": T, "iters_per_s": T / (t2 - t0), "solve_ms": 1e3 * (t2 - t0),
+           "init_ms": 1e3 * (t1 - t0), "iters_per_s_after_init": T / (t2 - t1),
+           "lanczos_steps_total": sum(q_schedule(T, inst.n)),
+           "objective": summ["objective"], "infeasibility_rel": summ["infeasibility"] / norm_b,
+           "eigen_residual_scaled": last["resid"],
+           "spmv": spmv_roofline(sv, inst, precision, spmv_reps, k)}
+    sv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,13 +414,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--T", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--batched-T", type=int, default=1000)
     ap.add_argument("--no-storage-optimal", action="store_true")
-    ap.add_argument("--probe-workload", type=int, default=2, choices=(2, 5),
+    ap.add_argument("--probe-workload", type=int, default=2, choices=(2, 3, 5),
                     help="workload of --traffic-probe")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only the SpMV kernel, 20 launches in each shape the autotuner chooses from (lanes per "
@@ -432,73 +470,61 @@ def main():
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
         return
 
+    norm_b = math.sqrt(float((inst.b * inst.b).sum()))
+    # headline: the plain-FP64 form (the paper's precision), whole solves of workload 2
+    s64 = Solve(inst, p64, torch)
+    dt64 = timed(s64, args.steps, args.warmup, torch)
+    progress(f"fp64 solves: {1e3 * dt64 / args.steps:.1f} ms each")
+    sum64 = s64.summary()
+    last64 = s64.record()
+    first64 = s64.record(0)
+    spmv64 = spmv_roofline(s64, inst, "fp64", 100, 2)
+    s64.close()
+    del s64
+
+    # FP32-stream form of the same workload: one warm-up and one timed solve
     s32 = Solve(inst, p32, torch)
-    dt32 = timed(s32, args.steps, args.warmup, torch)
-    progress(f"fp32 solves: {1e3 * dt32 / args.steps:.1f} ms each")
+    dt32 = timed(s32, 1, 1, torch)
+    progress(f"fp32 solve: {1e3 * dt32:.1f} ms")
     sum32 = s32.summary()
     infeas32 = s32.infeasibility_log()
     last32 = s32.record()
     first32 = s32.record(0)
-    norm_b = math.sqrt(float((inst.b * inst.b).sum()))
     cut_w, cut_j, cut_s = s32.round_cut()
-    # SpMV kernel leg: back-to-back launches on the solver's stream, HIP events
-    ms = C.c_double()
-    s32.lib.sketchycgal_time_spmv(s32.ctx, 200, C.byref(ms))
-    spmv_ms = ms.value
-    s32.close()
-    nnz_off = inst.nnz - inst.n
-    n = inst.n
-    # per nonzero: int32 column word (+ FP32 value when values are stored); per row: int32 row
-    # pointer, x (each entry once), shift s, u written
-    per_nz = 4 + (4 if sum32["matrix_format"] == 0 else 0)
-    bytes_per_launch = per_nz * nnz_off + 4 * (n + 1) + 4 * n + 4 * n + 4 * n
-    achieved = bytes_per_launch / (spmv_ms * 1e-3) / 1e9
-
-    # measured HBM bytes per launch of the shape the autotuner chose (same kernel source only)
-    traffic = measured_traffic(2, sum32)
-    gref = gather_reference(torch, n, nnz_off)
-    copy_gbs = copy_ceiling(torch)
-
-    fp64 = None
-    if not args.no_fp64:
-        s64 = Solve(inst, p64, torch)
-        dt64 = timed(s64, args.steps, args.warmup, torch)
-        progress(f"fp64 solves: {1e3 * dt64 / args.steps:.1f} ms each")
-        sum64 = s64.summary()
-        last64 = s64.record()
-        first64 = s64.record(0)
-        s64.close()
-        fp64 = {
-            "value": args.steps * T / dt64,
-            "ms_per_step": 1e3 * dt64 / args.steps,
-            "objective": sum64["objective"],
-            "infeasibility": sum64["infeasibility"],
-            "infeasibility_rel": sum64["infeasibility"] / norm_b,
-            "eigen_residual_scaled": last64["resid"],
-            "first_iteration_p_scaled": first64["p"],
-        }
-        # speedup at equal final infeasibility: the FP32 solve stopped at the first iteration whose
-        # ||diag X - b|| is at most the FP64 solve's final value, timed as a whole solve
-        hit = next((i + 1 for i, v in enumerate(infeas32) if v <= sum64["infeasibility"]), None)
-        if hit is not None:
-            s_eq = Solve(inst, Params(R=10, T=hit, seed=synth.CONFIG_SEEDS[2], precision="fp32"), torch)
-            dt_eq = timed(s_eq, 1, 0, torch)
-            s_eq.close()
-            fp64["equal_infeasibility"] = {
-                "fp32_iterations": hit, "fp32_ms": 1e3 * dt_eq, "fp64_iterations": T,
-                "fp64_ms": fp64["ms_per_step"], "speedup_fp32_vs_fp64": fp64["ms_per_step"] / (1e3 * dt_eq)}
-            progress(f"fp32 reaches the fp64 final infeasibility at t = {hit}: {1e3 * dt_eq:.1f} ms")
+    spmv32 = spmv_roofline(s32, inst, "fp32", 200, 2)
     ws32 = s32.nbytes
+    s32.close()
     del s32
+    # the same FP64 solve with its products summed in another order (another SpMV shape): how far rounding
+    # alone moves the whole-run result, the yardstick for the FP32-versus-FP64 difference
+    alt_lanes = 2 if spmv64["lanes_per_row"] != 2 else 4
+    s64b = Solve(inst, Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp64", autotune=0,
+                              spmv_lanes=alt_lanes), torch)
+    timed(s64b, 1, 0, torch)
+    sum64b = s64b.summary()
+    s64b.close()
+    del s64b
+    progress("fp64 solve with another summation order done")
+    # speedup at equal final infeasibility: the FP32 solve stopped at the first iteration whose
+    # ||diag X - b|| is at most the FP64 solve's final value, timed as a whole solve
+    equal = None
+    hit = next((i + 1 for i, v in enumerate(infeas32) if v <= sum64["infeasibility"]), None)
+    if hit is not None:
+        s_eq = Solve(inst, Params(R=10, T=hit, seed=synth.CONFIG_SEEDS[2], precision="fp32"), torch)
+        dt_eq = timed(s_eq, 1, 0, torch)
+        s_eq.close()
+        del s_eq
+        equal = {"fp32_iterations": hit, "fp32_ms": 1e3 * dt_eq, "fp64_iterations": T,
+                 "fp64_ms": 1e3 * dt64 / args.steps, "speedup_fp32_vs_fp64": (dt64 / args.steps) / dt_eq}
+        progress(f"fp32 reaches the fp64 final infeasibility at t = {hit}: {1e3 * dt_eq:.1f} ms")
 
     # storage-optimal mode: three Lanczos vectors (basis regenerated by a second sweep) and
     # Omega regenerated from its counters; same arithmetic, so the same iterates
     storage = None
     if not args.no_storage_optimal:
-        # the SpMV shape the autotuner picked for the stored-mode solve, so both run the same products
         pso = Params(R=10, T=T, seed=synth.CONFIG_SEEDS[2], precision="fp32", basis_mode=1, omega_mode=1,
-                     autotune=0, segments=sum32["spmv_segments"], spmv_lanes=sum32["spmv_lanes"],
-                     spmv_grid=sum32["spmv_grid"] if sum32["spmv_grid"] <= 2048 else 0)
+                     autotune=0, segments=spmv32["column_segments"], spmv_lanes=spmv32["lanes_per_row"],
+                     spmv_grid=spmv32["workgroups"] if spmv32["workgroups"] <= 2048 else 0)
         sso = Solve(inst, pso, torch)
         dtso = timed(sso, 1, 0, torch)
         sumso = sso.summary()
@@ -509,24 +535,45 @@ def main():
             "workspace_ratio": sso.nbytes / ws32,
             "objective_equals_stored_mode": sumso["objective"] == sum32["objective"],
         }
+        del sso
         progress(f"storage-optimal fp32 solve: {1e3 * dtso:.1f} ms")
+    gref = gather_reference(torch, inst.n, inst.nnz - inst.n)
+    copy_gbs = copy_ceiling(torch)
 
-    batched = None if args.no_batched else batched_leg(torch, args.batched_T, not args.no_fp64)
-    others = None
+    batched = None if args.no_batched else batched_leg(torch, args.batched_T, True)
+    others, w1 = None, None
     if not args.no_other_workloads:
         others = {}
-        for k, name in ((5, "random geometric, n=2^23, weights U[0.5,1.5]"),
-                        (3, "Chung-Lu power law, n=2^22, unit weights")):
-            others[f"workload_{k}"] = {"graph": name,
-                                       **{prec: spmv_line(torch, k, prec) for prec in ("fp32", "fp64")}}
-            progress(f"SpMV line for workload {k} done")
+        for k, name, Tk in ((5, "random geometric, n=2^23, ~2.0e7 edges, weights U[0.5,1.5]", 500),
+                            (3, "Chung-Lu power law (exponent 2.5), n=2^22, ~3.4e7 edges, unit weights", 1000)):
+            ik = synth.config_instance(k)
+            others[f"workload_{k}"] = {"graph": name, "n": ik.n, "nnz_offdiag": ik.nnz - ik.n,
+                                       "fp32": solve_leg(torch, k, ik, "fp32", Tk)}
+            del ik
+            progress(f"workload {k}: {others[f'workload_{k}']['fp32']['iters_per_s']:.2f} CGAL iterations/s")
         w1 = workload1_leg(torch)
         progress("workload 1 done")
-    else:
-        w1 = None
     cpu = None if args.no_cpu else cpu_baseline(inst, T, args.cpu_seconds)
 
-    value = args.steps * T / dt32
+    # the roofline object: the Lanczos SpMV of the largest workload (its working set far exceeds the
+    # 256 MB last-level cache, so the bandwidth is HBM bandwidth), else the headline workload's FP32 kernel
+    rl_src, rl_name = spmv32, "workload 2 (torus, n=2^20) Lanczos SpMV, FP32"
+    if others is not None:
+        rl_src, rl_name = others["workload_5"]["fp32"]["spmv"], "workload 5 (random geometric, n=2^23) Lanczos SpMV, FP32"
+    roofline = {
+        "bound": "hbm",
+        "kernel": rl_src["kernel"] + " (" + rl_name + ")",
+        "achieved": rl_src["achieved_GBps"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": rl_src["achieved_GBps"] / HBM_PEAK_GBS,
+        "traffic": rl_src["traffic"],
+        "algorithmic_bytes_per_launch": rl_src["algorithmic_bytes_per_product"],
+        "avg_launch_us": rl_src["avg_product_us"],
+        "copy_ceiling_GBps": copy_gbs,
+        "frac_of_copy_ceiling": rl_src["achieved_GBps"] / copy_gbs,
+    }
+    value = args.steps * T / dt64
     out = {
         "metric": "CGAL iters/sec + Lanczos SpMV HBM GB/s (% peak), FP32/batched vs FP64 plain",
         "value": value,
@@ -534,57 +581,41 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt32 / args.steps,
+        "ms_per_step": 1e3 * dt64 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "MaxCut SDP, 1024x1024 torus + 2n random long-range edges, weights +-1, "
-                        "n=1048576, R=10, T=%d, q_t=ceil(t^(1/4) ln n), FP32-stream/FP64-critical" % T,
-            "n": n, "nnz_offdiag": nnz_off, "R": 10, "T": T, "lanczos_steps_total": sum(qs),
+            "workload": "MaxCut SDP plain FP64, 1024x1024 torus + 2n random long-range edges, weights +-1, "
+                        "n=1048576, R=10, T=%d, q_t=ceil(t^(1/4) ln n)" % T,
+            "n": inst.n, "nnz_offdiag": inst.nnz - inst.n, "R": 10, "T": T, "lanczos_steps_total": sum(qs),
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": spmv_kernel_name(sum32) + " (Lanczos SpMV with diagonal shift, FP32)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": spmv_ms * 1e3,
-            "copy_ceiling_GBps": copy_gbs,
-            "frac_of_copy_ceiling": achieved / copy_gbs,
-            "gathers_per_s": nnz_off / (spmv_ms * 1e-3),
+        "roofline": roofline,
+        "result_fp64": {"objective": sum64["objective"], "infeasibility_rel": sum64["infeasibility"] / norm_b,
+                        "eigen_residual_scaled": last64["resid"], "spmv": spmv64,
+                        "objective_rel_diff_other_summation_order": abs(sum64b["objective"] - sum64["objective"]) /
+                        abs(sum64["objective"]),
+                        "other_summation_order_lanes": alt_lanes},
+        "fp32_stream": {
+            "value": T / dt32, "unit": "CGAL iters/s", "ms_per_step": 1e3 * dt32,
+            "speedup_vs_fp64": (T / dt32) / value, "equal_infeasibility": equal,
+            "objective": sum32["objective"], "infeasibility_rel": sum32["infeasibility"] / norm_b,
+            "eigen_residual_scaled": last32["resid"], "xi_scaled": last32["xi"],
+            # whole runs follow rounding: the FP64 solve with another summation order above is the yardstick
+            "objective_rel_diff_vs_fp64": abs(sum32["objective"] - sum64["objective"]) / abs(sum64["objective"]),
+            # from the same (zero) state: the per-iteration FP32-stream error
+            "first_iteration_objective_rel_diff_vs_fp64": abs(first32["p"] - first64["p"]) / abs(first64["p"]),
+            "rounded_cut_weight": cut_w, "rounded_cut_column": cut_j, "rounding_ms": 1e3 * cut_s,
+            "cut_over_sdp_objective": cut_w / -sum32["objective"],
+            "spmv": spmv32,
+            "gathers_over_uniform_reference": spmv32["gathers_per_s"] / gref,
             "uniform_gather_reference_per_s": gref,
-            "gathers_over_uniform_reference": nnz_off / (spmv_ms * 1e-3) / gref,
-            "uniform_gather_reference_method": "torch.index_select of nnz_offdiag uniform random int32 indices from "
-                                               "an n-entry FP32 vector on the same GPU (the SpMV makes one gather per "
-                                               "off-diagonal entry; half of the torus's are local, none here)",
         },
-        "spmv_tuning": {"kernel": spmv_kernel_name(sum32), "lanes_per_row": sum32["spmv_lanes"],
-                        "column_segments": sum32["spmv_segments"],
-                        "workgroups": sum32["spmv_grid"],
-                        "matrix_format": ["values", "columns only", "columns with sign bit"][sum32["matrix_format"]]},
-        "fp64_plain": fp64,
-        "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
-        "result_fp32": {"objective": sum32["objective"], "infeasibility": sum32["infeasibility"],
-                        "infeasibility_rel": sum32["infeasibility"] / norm_b,
-                        "eigen_residual_scaled": last32["resid"], "xi_scaled": last32["xi"],
-                        "objective_rel_diff_vs_fp64": (abs(sum32["objective"] - fp64["objective"]) /
-                                                       abs(fp64["objective"])) if fp64 else None,
-                        # from the same (zero) state: the per-iteration FP32-stream error, which
-                        # the whole-run difference above compounds through rounding-sensitive iterates
-                        "first_iteration_objective_rel_diff_vs_fp64": (
-                            abs(first32["p"] - fp64["first_iteration_p_scaled"]) /
-                            abs(fp64["first_iteration_p_scaled"])) if fp64 else None,
-                        "rounded_cut_weight": cut_w, "rounded_cut_column": cut_j, "rounding_ms": 1e3 * cut_s,
-                        "cut_over_sdp_objective": cut_w / -sum32["objective"]},
         "storage_optimal_fp32": storage,
         "batched": batched,
-        "spmv_other_workloads": others,
+        "other_workloads": others,
         "workload_1": w1,
         "cpu_baseline": cpu,
     }
