@@ -85,7 +85,11 @@ typedef struct {
                                runs when the matrix has at least 2^20 off-diagonal entries or
                                segments is set                                                */
     int32_t  segments;      /* column segments of the SpMV: 0 = chosen by the autotuner
-                               (1 below 1M nonzeros), or 1, 2, 4                              */
+                               (1 below 1M nonzeros), or 1, 2, 4 (one launch per segment,
+                               each adding into the product), or 8 (all eight in one launch,
+                               segment s on the workgroups the s-th XCD dispatches, so each
+                               XCD gathers from one eighth of x; their raw row sums go to a
+                               workspace buffer and a second pass adds them up)               */
     int32_t  spmv_lanes;    /* lanes per row of the SpMV reduction: 0 = autotuned / by mean
                                row length, or 2, 4, 8, 16, 32; 1 = the quad-chunk product
                                (each row's column words padded to 16-byte quads, rows packed
@@ -146,7 +150,7 @@ typedef struct {
     double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
     int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction (1: the
                                  quad-chunk product)                                            */
-    int32_t spmv_segments;    /* column segments of the SpMV                                   */
+    int32_t spmv_segments;    /* column segments of the SpMV (8: the concurrent form)          */
     int32_t matrix_format;    /* storage of the off-diagonal values: 0 values, 1 columns only
                                  (common value), 2 columns with sign bit (common magnitude)  */
     int32_t spmv_grid;        /* workgroups of the SpMV launch                                 */

@@ -56,8 +56,18 @@ int64_t quad_chunk_cap(const scg_params& p, int64_t n, int64_t nnz) {
     return dq / 33 + 2;
 }
 
+// Column segments the SpMV may use with these parameters: kSegMax when the
+// autotuner may try them (or they are forced), else 1.  Sizes the segment row
+// pointers, the row-block descriptors and the concurrent-segment partials.
+int seg_cap(const scg_params& p, int64_t n, int64_t nnz) {
+    if (p.segments > 1) return kSegMax;
+    if (p.segments == 0 && p.autotune && n >= (1 << 18) && nnz >= (1 << 20) && p.spmv_lanes != 1) return kSegMax;
+    return 1;
+}
+
 struct Layout {
-    size_t rp, col, val, dC, b, z, y, s, V, u, v, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, qw, qc, total;
+    size_t rp, col, val, dC, b, z, y, s, V, u, v, xp, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, qw, qc,
+        total;
     size_t recon_bytes;
 };
 
@@ -69,7 +79,8 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     const size_t ld = (size_t)((n + 63) / 64 * 64);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    L.rp = take(sizeof(int32_t) * (size_t)kSegMax * (n + 1));
+    const int nsc = seg_cap(p, n, nnz);
+    L.rp = take(sizeof(int32_t) * (size_t)nsc * (n + 1));
     L.col = take(sizeof(int32_t) * (size_t)nnz);
     L.val = take(es * (size_t)nnz);
     L.dC = take(8 * n);
@@ -81,9 +92,10 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.V = take(es * ld * (size_t)(p.basis_mode == 1 ? 3 : qm + 1));
     L.u = take(es * n);
     L.v = take(es * n);
+    L.xp = take(nsc > 1 ? es * ld * (size_t)kSegMax : 0);   // concurrent-segment row sums
     L.Om = take(p.omega_mode == 1 ? 0 : es * ld * R);   // generated from Philox where used
     L.S = take(es * ld * R);
-    L.rb = take(sizeof(int2) * (size_t)kSegMax * (n + 2));
+    L.rb = take(sizeof(int2) * (size_t)nsc * (n + 2));
     L.sc = take(sizeof(DevScalars));
     const size_t pw = 19 + (size_t)kRMax + (size_t)qm + 2;   // slices of Prob (scg_internal.hpp)
     L.part = take(8 * (size_t)kGMax * pw);
@@ -156,11 +168,45 @@ Prob<T> prob(scg_ctx* c) {
 }
 
 template <typename T, int MODE, int RB, int FMT>
+void launch_spmv_x(scg_ctx* c, const T* x, int step, int lanes) {
+    Prob<T> P = prob<T>(c);
+    dim3 g(c->Gs), b(kBlock);
+    SegArgs sg{};
+    sg.first = 1;
+    sg.last = 1;
+    sg.lanczos = (MODE == SPMV_LANCZOS) ? 1 : 0;
+    for (int s = 0; s < kSegMax; ++s) {
+        sg.xrp[s] = c->rp_seg[s];
+        sg.xrbd[s] = c->rbd_seg[s];
+        sg.xnrb[s] = c->nrb_seg[s];
+    }
+    sg.xpart = c->xpart;
+    sg.xld = c->ld;
+    switch (lanes) {
+        case 2: hipLaunchKernelGGL((k_spmv<T, 2, SPMV_XPART, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+        case 4: hipLaunchKernelGGL((k_spmv<T, 4, SPMV_XPART, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+        case 8: hipLaunchKernelGGL((k_spmv<T, 8, SPMV_XPART, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+        case 16: hipLaunchKernelGGL((k_spmv<T, 16, SPMV_XPART, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+        default: hipLaunchKernelGGL((k_spmv<T, 32, SPMV_XPART, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
+    }
+    hipLaunchKernelGGL((k_xcombine<T, MODE>), g, b, 0, c->stream, P, x, step, (const T*)c->xpart, (int64_t)c->ld);
+}
+
+template <typename T, int MODE, int RB, int FMT>
 void launch_spmv_f(scg_ctx* c, const T* x, int step, int lanes) {
+    if (c->xseg) {
+        launch_spmv_x<T, MODE, RB, FMT>(c, x, step, lanes);
+        return;
+    }
     Prob<T> P = prob<T>(c);
     dim3 g(c->Gs), b(kBlock);
     for (int sgi = 0; sgi < c->nseg; ++sgi) {
-        SegArgs sg{c->rp_seg[sgi], c->rbd_seg[sgi], c->nrb_seg[sgi], sgi == 0, sgi == c->nseg - 1};
+        SegArgs sg{};
+        sg.rp = c->rp_seg[sgi];
+        sg.rbd = c->rbd_seg[sgi];
+        sg.nrb = c->nrb_seg[sgi];
+        sg.first = (sgi == 0);
+        sg.last = (sgi == c->nseg - 1);
         switch (lanes) {
             case 2: hipLaunchKernelGGL((k_spmv<T, 2, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
             case 4: hipLaunchKernelGGL((k_spmv<T, 4, MODE, RB, FMT>), g, b, 0, c->stream, P, x, step, sg); break;
@@ -493,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_segcount(int64_t n, const int64_t* r
     int64_t lo, hi;
     split_range(n, xcd_lid(), gridDim.x, lo, hi);
     for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-        int32_t cs[kSegMax] = {0, 0, 0, 0};
+        int32_t cs[kSegMax] = {};
         for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
             const int32_t j = col[e];
             if ((int64_t)j == r) continue;
@@ -664,10 +710,22 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
     const double mean = c->n > 0 ? (double)c->nnz_off / (double)c->n : 1.0;
     float best = 1e30f;
     int best_l = c->lanes, best_s = 1, best_g = 0;
+    // average of five launches after one warm-up, HIP events on the context stream
+    auto time_lanes = [&](int l, float& ms) -> hipError_t {
+        launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, l);
+        hipError_t e = hipEventRecord(e0, c->stream);
+        if (e != hipSuccess) return e;
+        for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, l);
+        if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        return hipEventElapsedTime(&ms, e0, e1);
+    };
+    const int cap = (int)(c->rb_cap / (size_t)(c->n + 2));   // segments the workspace was sized for
+    bool best_x = false;
     for (int nseg : {1, 2, 4}) {
         if (c->prm.segments > 0 && nseg != c->prm.segments) continue;
         if (nseg > 1) {
-            if (c->prm.segments == 0 && c->n < (1 << 18)) break;
+            if (nseg > cap || (c->prm.segments == 0 && c->n < (1 << 18))) break;
             scg_status st = build_segments<T>(c, nseg, row_ptr, col, val);
             if (st != SCG_OK) return st;
         }
@@ -681,17 +739,32 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
             for (int l : {2, 4, 8, 16, 32}) {
                 if (c->prm.spmv_lanes > 0 && l != c->prm.spmv_lanes) continue;
                 if (c->prm.spmv_lanes == 0 && l > 4 * mean + 4) break;
-                launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, l);   // warm-up
-                HIP_TRY(hipEventRecord(e0, c->stream));
-                for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, l);
-                HIP_TRY(hipEventRecord(e1, c->stream));
-                HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                HIP_TRY(time_lanes(l, ms));
                 if (ms < best) { best = ms; best_l = l; best_s = nseg; best_g = gcap; }
             }
         }
         c->Gs = g_nat;
+    }
+    // eight segments in one launch, one per XCD, and the combining pass
+    if (cap >= kSegMax && c->xpart && (c->prm.segments == kSegMax || (c->prm.segments == 0 && c->n >= (1 << 18))) &&
+        c->prm.spmv_lanes != 1) {
+        scg_status st = build_segments<T>(c, kSegMax, row_ptr, col, val);
+        if (st != SCG_OK) return st;
+        const int g_keep = c->Gs;
+        c->xseg = true;
+        for (int g : {2048, 1024}) {
+            if (c->prm.spmv_grid > 0 && g != 2048) continue;   // a forced grid is applied afterwards
+            c->Gs = g;
+            for (int l : {2, 4, 8}) {
+                if (c->prm.spmv_lanes > 0 && l != c->prm.spmv_lanes) continue;
+                float ms = 0.f;
+                HIP_TRY(time_lanes(l, ms));
+                if (ms < best) { best = ms; best_l = l; best_s = kSegMax; best_g = g; best_x = true; }
+            }
+        }
+        c->xseg = false;
+        c->Gs = g_keep;
     }
     // the quad-chunk product, when the matrix has that layout
     if (c->nqc > 0 && (c->prm.spmv_lanes == 0 || c->prm.spmv_lanes == 1) && c->prm.segments <= 1) {
@@ -699,13 +772,8 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         for (int g : {1536, 2048}) {
             if (c->prm.spmv_grid > 0 && g != 1536) continue;   // a forced grid is applied afterwards
             c->Gs = g;
-            launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, 1);   // warm-up
-            HIP_TRY(hipEventRecord(e0, c->stream));
-            for (int r = 0; r < 5; ++r) launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, 1);
-            HIP_TRY(hipEventRecord(e1, c->stream));
-            HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            HIP_TRY(time_lanes(1, ms));
             if (ms < best) { best = ms; best_l = 1; best_s = 1; best_g = g; }
         }
         c->Gs = g_keep;
@@ -716,7 +784,8 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         scg_status st = build_segments<T>(c, best_s, row_ptr, col, val);
         if (st != SCG_OK) return st;
     }
-    if (best_l == 1) c->Gs = best_g;
+    c->xseg = best_x;
+    if (best_l == 1 || best_x) c->Gs = best_g;
     else if (best_g != 0) c->Gs = std::min(c->Gs, best_g);
     c->lanes = best_l;
     return SCG_OK;
@@ -831,6 +900,10 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     } else if (c->prm.segments > 1) {
         scg_status st = build_segments<T>(c, c->prm.segments, row_ptr, col, val);
         if (st != SCG_OK) return st;
+        if (c->prm.segments == kSegMax) {   // the concurrent form
+            c->xseg = true;
+            c->Gs = kGMax;
+        }
     }
     // forced SpMV shape (overrides the autotuner); the quad-chunk product needs its layout
     if (c->prm.spmv_lanes == 1 && c->nqc == 0) return SCG_EINVAL;
@@ -855,6 +928,8 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     const int l = p->spmv_lanes;
     if (l != 0 && l != 1 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
     if (l == 1 && (p->segments > 1 || p->matrix_format == 1)) return false;   // the quad-chunk product
+    if (p->segments != 0 && p->segments != 1 && p->segments != 2 && p->segments != 4 && p->segments != kSegMax)
+        return false;
     if (p->spmv_grid < 0 || p->spmv_grid > kGMax) return false;
     if (p->basis_mode != 0 && p->basis_mode != 1) return false;
     if (p->basis_mode == 1 && p->reorth == 2) return false;   // full reorthogonalisation needs the stored basis
@@ -940,7 +1015,9 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->hi = (p->constraint_set == 1) ? (double*)(base + L.hi) : nullptr;
     c->S = base + L.S;
     c->rb = (int32_t*)(base + L.rb);
-    c->rb_cap = (size_t)kSegMax * (n + 2);
+    c->rb_cap = (size_t)seg_cap(*p, n, nnz) * (n + 2);
+    c->xpart = (seg_cap(*p, n, nnz) > 1) ? (void*)(base + L.xp) : nullptr;
+    c->xseg = false;
     c->sc = (DevScalars*)(base + L.sc);
     c->part = (double*)(base + L.part);
     c->counter = (unsigned*)(base + L.counter);

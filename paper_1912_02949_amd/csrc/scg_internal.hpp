@@ -12,7 +12,7 @@ constexpr int kRMax = 32;      // maximum sketch size R
 constexpr int kNB = 512;       // nonzeros staged through LDS per row block (one wave)
 constexpr int kRowsCap = 128;  // rows per row block
 constexpr int kGMax = 2048;    // workgroups of a streaming launch
-constexpr int kSegMax = 4;     // column segments of the SpMV
+constexpr int kSegMax = 8;     // column segments of the SpMV (8: one per XCD, run concurrently)
 
 // Storage of the off-diagonal values of C.
 enum MatFmt {
@@ -110,7 +110,8 @@ struct scg_ctx {
     int G;          // workgroups for vector kernels
     int Gs;         // workgroups for SpMV kernels
     int lanes;      // lanes per row in the SpMV row reduction; 1: the quad-chunk product
-    int nseg;       // column segments (1, 2 or 4): launch s gathers only x[s*seglen, (s+1)*seglen)
+    int nseg;       // column segments (1, 2, 4 or 8): segment s gathers only x[s*seglen, (s+1)*seglen)
+    bool xseg;      // 8 segments in one launch, segment s on XCD s, partial row sums combined by a second pass
     int64_t seglen;
     int32_t* rp_seg[scg::kSegMax];   // per segment: row pointers into col/val (absolute)
     int2* rbd_seg[scg::kSegMax];     // per segment: row-block descriptors (first row, first nonzero)
@@ -134,6 +135,7 @@ struct scg_ctx {
     void* V;
     void* u;
     void* v;
+    void* xpart;    // per-segment raw row sums of the concurrent-segment product (kSegMax x ld), or null
     void* Om;
     void* S;
     int32_t* rb;

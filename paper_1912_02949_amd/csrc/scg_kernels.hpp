@@ -36,7 +36,7 @@
 
 namespace scg {
 
-enum SpmvMode { SPMV_LANCZOS = 0, SPMV_OBJ = 1, SPMV_APPLY = 2 };
+enum SpmvMode { SPMV_LANCZOS = 0, SPMV_OBJ = 1, SPMV_APPLY = 2, SPMV_XPART = 3 };
 
 // Partial-sum widths of the producers.
 constexpr int kWPrep = 6, kWSpmv = 1, kWUpd = 1, kWObj = 2, kWPrimal = 4;
@@ -71,6 +71,9 @@ __device__ __forceinline__ int4 load_cols4(const int* p) {
     const i32x4_t t = *reinterpret_cast<const i32x4_t*>(p);
     return make_int4(t.x, t.y, t.z, t.w);
 }
+
+// Rows of the quad starting at row r (the last quad of a vector may be partial).
+__device__ __forceinline__ int quad_rows(int64_t r, int64_t n) { return (int)((n - r < 4) ? (n - r) : 4); }
 
 template <int LANES, typename A>
 __device__ __forceinline__ A group_sum(A v) {
@@ -196,12 +199,26 @@ __device__ __forceinline__ void store_products(int e0, int e1, int lane, const T
 // columns fall in segment `seg`.  Launches over the segments run in order;
 // all but the last store the raw row sums in u, the later ones add them.
 // rbd[k] = (first row, first nonzero) of row block k; rbd[nrb] = (n, end).
+//
+// SPMV_XPART runs all kSegMax segments in one launch: workgroup b works on
+// segment b mod 8, i.e. on the XCD that dispatches it, so each XCD's L2 only
+// ever holds its own eighth of x; it stores the raw row sums of its segment
+// in xpart[seg * xld + r], and k_xcombine adds the eight partials of each row
+// and finishes the product.  A Lanczos product (lanczos = 1) returns early
+// once the recurrence has ended.
 struct SegArgs {
     const int32_t* rp;
     const int2* rbd;
     int nrb;
     int first;
     int last;
+    // SPMV_XPART only
+    int lanczos;
+    const int32_t* xrp[kSegMax];
+    const int2* xrbd[kSegMax];
+    int xnrb[kSegMax];
+    void* xpart;
+    int64_t xld;
 };
 
 // Scale of the vector being multiplied, shared by both product kernels.
@@ -259,8 +276,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
     __shared__ int rbeg_all[kWaves][kRowsCap + 1];
     __shared__ double wred[kWaves][2];
     DevScalars* sc = P.sc;
-    if (MODE == SPMV_LANCZOS && sc->done) return;
+    if ((MODE == SPMV_LANCZOS || (MODE == SPMV_XPART && sg.lanczos)) && sc->done) return;
     P.rp = sg.rp;
+    const int2* rbd = sg.rbd;
+    int nrb = sg.nrb, lid = xcd_lid(), ng = gridDim.x, seg = 0;
+    if (MODE == SPMV_XPART) {   // segment = the dispatching XCD; the XCD's workgroups split its row blocks
+        seg = blockIdx.x % kXcd;
+        P.rp = sg.xrp[seg];
+        rbd = sg.xrbd[seg];
+        nrb = sg.xnrb[seg];
+        lid = blockIdx.x / kXcd;
+        ng = gridDim.x / kXcd;
+    }
+    T* xpart = (MODE == SPMV_XPART) ? static_cast<T*>(sg.xpart) + (size_t)seg * sg.xld : nullptr;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     T* stage = stage_all[wv];
     T* xrow = xrow_all[wv];
@@ -268,22 +296,26 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
     T* rsum = rsum_all[wv];
     int* rbeg = rbeg_all[wv];
     int64_t blo, bhi;
-    split_range(sg.nrb, xcd_lid() * kWaves + wv, gridDim.x * kWaves, blo, bhi);
+    split_range(nrb, lid * kWaves + wv, ng * kWaves, blo, bhi);
     // first block's descriptors and nonzeros are requested before the scale reduction
     int2 dA = make_int2(0, 0), dB = make_int2(0, 0), dC = make_int2(0, 0);
     BlockRegs<T, FMT> cur;
     if (blo < bhi) {
-        dA = sg.rbd[blo];
-        dB = sg.rbd[blo + 1];
-        if (blo + 1 < bhi) dC = sg.rbd[blo + 2];
+        dA = rbd[blo];
+        dB = rbd[blo + 1];
+        if (blo + 1 < bhi) dC = rbd[blo + 2];
         if (!(dB.x - dA.x == 1 && dB.y - dA.y > kNB)) fetch_block<T, FMT>(P, dA.y, dB.y, lane, cur);
     }
     double xs = 1.0;
-    if (!spmv_scale<MODE>(P, step, sg.last, xs)) return;
+    if (MODE != SPMV_XPART && !spmv_scale<MODE>(P, step, sg.last, xs)) return;
     const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
     double acc0 = 0.0, acc1 = 0.0;
     const double cv = (FMT == FMT_VAL) ? 1.0 : P.cval;
     auto finish_row = [&](int r, double off_raw, double xr, double sr) {
+        if (MODE == SPMV_XPART) {
+            xpart[r] = (T)off_raw;
+            return;
+        }
         if (!sg.first) off_raw += (double)P.u[r];
         if (!sg.last) {
             P.u[r] = (T)off_raw;
@@ -311,13 +343,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
         const bool has_next = rbk + 1 < bhi;
         const bool next_long = has_next && (dC.x - dB.x == 1 && dC.y - dB.y > kNB);
         int2 dD = dC;
-        if (rbk + 2 < bhi) dD = sg.rbd[rbk + 3];
+        if (rbk + 2 < bhi) dD = rbd[rbk + 3];
         if (nrows == 1 && e1 - e0 > kNB) {
             if (has_next && !next_long) fetch_block<T, FMT>(P, dB.y, dC.y, lane, cur);
             T a = 0;
             for (int e = e0 + lane; e < e1; e += 64) a += nz_product<T, FMT>(P, x, e, stream_load(P.col + e));
             const double tot = wave_sum((double)a);
-            if (lane == 0) finish_row(r0, tot, (double)x[r0], (double)P.s[r0]);
+            if (lane == 0)
+                finish_row(r0, tot, (MODE == SPMV_XPART) ? 0.0 : (double)x[r0],
+                           (MODE == SPMV_XPART) ? 0.0 : (double)P.s[r0]);
         } else {
             // (A) the block's row data, its gathers and the next block's entries are
             // all in flight before any of them is consumed
@@ -327,8 +361,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
             for (int h = 0; h < kRowsCap / 64; ++h) {
                 const int i = lane + 64 * h;
                 if (i < nrows) {
-                    xr_r[h] = x[r0 + i];
-                    sr_r[h] = stream_load(P.s + r0 + i);
+                    // the segment partials need neither x_r nor the shift
+                    xr_r[h] = (MODE == SPMV_XPART) ? (T)0 : x[r0 + i];
+                    sr_r[h] = (MODE == SPMV_XPART) ? (T)0 : stream_load(P.s + r0 + i);
                     rb_r[h] = stream_load(P.rp + r0 + i) - e0;
                 }
             }
@@ -369,7 +404,91 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Prob<T> P, const T* __restrict_
         dB = dC;
         dC = dD;
     }
-    if (MODE == SPMV_APPLY || !sg.last) return;
+    if (MODE == SPMV_APPLY || MODE == SPMV_XPART || !sg.last) return;
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    if (lane == 0) {
+        wred[wv][0] = acc0;
+        wred[wv][1] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i < kWaves; ++i) {
+            s0 += wred[i][0];
+            s1 += wred[i][1];
+        }
+        if (MODE == SPMV_LANCZOS) {
+            P.p_spmv[blockIdx.x] = s0;
+        } else {
+            P.p_obj[(size_t)blockIdx.x * 2 + 0] = s0;
+            P.p_obj[(size_t)blockIdx.x * 2 + 1] = s1;
+        }
+    }
+}
+
+// Second pass of the concurrent-segment product: row r's off-diagonal sum is
+// the sum of its eight segment partials (segment order, FP64), then the shift,
+// the scale and the partial sums exactly as the last segment of k_spmv.  Rows
+// go four to a lane as 16-byte quads; the first quad's loads are in flight
+// before the scale reduction.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_xcombine(Prob<T> P, const T* __restrict__ x, int step,
+                                                     const T* __restrict__ xpart, int64_t xld) {
+    __shared__ double wred[kWaves][2];
+    DevScalars* sc = P.sc;
+    if (MODE == SPMV_LANCZOS && sc->done) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t n = P.n;
+    int64_t qlo, qhi;
+    split_range((n + 3) / 4, xcd_lid(), gridDim.x, qlo, qhi);
+    int64_t qd = qlo + threadIdx.x;
+    double off[4] = {0.0, 0.0, 0.0, 0.0};
+    // the partial vectors have stride xld (a multiple of 64): a quad never leaves them
+    auto load_offs = [&](int64_t q) {
+        const int64_t r = 4 * q;
+        T pv[kSegMax][4];
+#pragma unroll
+        for (int sgi = 0; sgi < kSegMax; ++sgi) load_vals4(xpart + (size_t)sgi * xld + r, pv[sgi]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double a = 0.0;
+#pragma unroll
+            for (int sgi = 0; sgi < kSegMax; ++sgi) a += (double)pv[sgi][i];
+            off[i] = a;
+        }
+    };
+    if (qd < qhi) load_offs(qd);
+    double xs = 1.0;
+    if (!spmv_scale<MODE>(P, step, true, xs)) return;
+    const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
+    const double cv = P.cval;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (; qd < qhi; qd += kBlock) {
+        if (qd != qlo + threadIdx.x) load_offs(qd);
+        const int64_t r = 4 * qd;
+        const int m = quad_rows(r, n);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i >= m) break;
+            const double xr = (double)x[r + i], sr = (double)P.s[r + i];
+            const double o = off[i] * cv;
+            if (MODE == SPMV_LANCZOS) {
+                const T ut = (T)((o + sr * xr) * xs);
+                P.u[r + i] = ut;
+                acc0 += xr * xs * (double)ut;
+            } else if (MODE == SPMV_OBJ) {
+                const double cvr = (o + P.dC[r + i] * xr) * xs;
+                const double dvr = (o + sr * xr) * xs;
+                acc0 += xr * xs * cvr;
+                const double rr = dvr - xi * xr * xs;
+                acc1 += rr * rr;
+            } else {
+                P.u[r + i] = (T)(o + sr * xr);
+            }
+        }
+    }
+    if (MODE == SPMV_APPLY) return;
     acc0 = wave_sum(acc0);
     acc1 = wave_sum(acc1);
     if (lane == 0) {
@@ -507,7 +626,6 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
     split_range(((n) + 3) / 4, xcd_lid(), gridDim.x, qlo_, qhi_);          \
     for (int64_t qd = qlo_ + threadIdx.x; qd < qhi_; qd += kBlock)
 
-__device__ __forceinline__ int quad_rows(int64_t r, int64_t n) { return (int)((n - r < 4) ? (n - r) : 4); }
 
 // omega_step from the SpMV partials; w = u - omega v_step - rho v_{step-1}
 // stored as V[step+1]; partial sums of ||w||^2 (unless reorthogonalising).

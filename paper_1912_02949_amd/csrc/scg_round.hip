@@ -21,14 +21,17 @@ namespace {
 
 __device__ __forceinline__ double sgn1(double u) { return (u < 0.0) ? -1.0 : 1.0; }
 
+// Row pointers of the column segments the stored matrix is split into.
+struct SegRows {
+    const int32_t* rp[kSegMax];
+};
+
 // Partials per workgroup: [0, R) sum_r chi_j(r) (C_off chi_j)_r in scaled units, [R] sum_r diag_r.
 template <typename T, int FMT, int RB>
-__global__ __launch_bounds__(kBlock) void k_cut_forms(int64_t n, int nseg, const int32_t* rp0, const int32_t* rp1,
-                                                      const int32_t* rp2, const int32_t* rp3, const int32_t* col,
+__global__ __launch_bounds__(kBlock) void k_cut_forms(int64_t n, int nseg, SegRows sr, const int32_t* col,
                                                       const T* val, double cval, const double* dC, const double* U,
                                                       int R, double* part) {
     __shared__ double red[kWaves];
-    const int32_t* rps[4] = {rp0, rp1, rp2, rp3};
     double acc[RB + 1];
 #pragma unroll
     for (int j = 0; j <= RB; ++j) acc[j] = 0.0;
@@ -37,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_forms(int64_t n, int nseg, const
 #pragma unroll
         for (int j = 0; j < RB; ++j) off[j] = 0.0;
         for (int sg = 0; sg < nseg; ++sg) {
-            const int32_t* rp = rps[sg];
+            const int32_t* rp = sr.rp[sg];
             for (int e = rp[r]; e < rp[r + 1]; ++e) {
                 const int cw = col[e];
                 const int c = (FMT == FMT_SGN) ? (cw & 0x7fffffff) : cw;
@@ -66,15 +69,15 @@ __global__ __launch_bounds__(kBlock) void k_cut_indicator(int64_t n, const doubl
 
 template <typename T, int FMT>
 void launch_forms(scg_ctx* c, const double* U, int RBsel) {
-    const int32_t* rp[4] = {c->rp_seg[0], c->rp_seg[0], c->rp_seg[0], c->rp_seg[0]};
-    for (int s = 0; s < c->nseg; ++s) rp[s] = c->rp_seg[s];
+    SegRows sr{};
+    for (int s = 0; s < kSegMax; ++s) sr.rp[s] = c->rp_seg[(s < c->nseg) ? s : 0];
     const dim3 g(c->G), b(kBlock);
     if (RBsel == 8)
-        hipLaunchKernelGGL((k_cut_forms<T, FMT, 8>), g, b, 0, c->stream, (int64_t)c->n, c->nseg, rp[0], rp[1], rp[2],
-                           rp[3], c->col, (const T*)c->val, c->cval, c->dC, U, c->prm.R, c->part);
+        hipLaunchKernelGGL((k_cut_forms<T, FMT, 8>), g, b, 0, c->stream, (int64_t)c->n, c->nseg, sr, c->col,
+                           (const T*)c->val, c->cval, c->dC, U, c->prm.R, c->part);
     else
-        hipLaunchKernelGGL((k_cut_forms<T, FMT, kRMax>), g, b, 0, c->stream, (int64_t)c->n, c->nseg, rp[0], rp[1],
-                           rp[2], rp[3], c->col, (const T*)c->val, c->cval, c->dC, U, c->prm.R, c->part);
+        hipLaunchKernelGGL((k_cut_forms<T, FMT, kRMax>), g, b, 0, c->stream, (int64_t)c->n, c->nseg, sr, c->col,
+                           (const T*)c->val, c->cval, c->dC, U, c->prm.R, c->part);
 }
 
 template <typename T>

@@ -156,25 +156,32 @@ def test_trajectory_small_q_fp64(cfg1, reorth):
     assert rel(summ["infeasibility"], ref.infeasibility) < 1e-9
 
 
-@pytest.mark.parametrize("segments", [2, 4])
-@pytest.mark.parametrize("which", ["cfg1", "star", "pm1"])
-def test_apply_with_column_segments(which, segments, cfg1):
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+@pytest.mark.parametrize("segments", [2, 4, 8])
+@pytest.mark.parametrize("which", ["cfg1", "star", "pm1", "odd"])
+def test_apply_with_column_segments(which, segments, precision, tol, cfg1):
+    # 8 segments: all in one launch (segment s on XCD s) plus the combining pass;
+    # "odd" has n = 4099, so the last segment and the last row quad are partial
     need_gpu()
     inst = {"cfg1": lambda: cfg1, "star": lambda: _star_plus(5000, 3),
-            "pm1": lambda: synth.laplacian_instance(synth.torus_longrange(64, 5))}[which]()
-    s = make_solver(inst, R=4, T=5, seed=1, segments=segments)
+            "pm1": lambda: synth.laplacian_instance(synth.torus_longrange(64, 5)),
+            "odd": lambda: synth.laplacian_instance(synth.erdos_renyi(4099, 30000, 13))}[which]()
     rng = np.random.default_rng(0)
     x = rng.standard_normal(inst.n)
-    y = s.apply(x).cpu().numpy()
     Cs, bs, _, _ = scale_problem(inst.to_scipy(), inst.b, float(inst.n))
     ref = Cs @ x + math.sqrt(2.0) * (0 - bs) * x
-    assert maxrel(y, ref) < 1e-13
+    for grid in (0, 8, 64):
+        s = make_solver(inst, R=4, T=5, seed=1, segments=segments, spmv_grid=grid, precision=precision)
+        assert s.summary()["spmv_segments"] == segments
+        y = s.apply(x).cpu().numpy()
+        assert maxrel(y, ref) < tol, grid
 
 
-def test_trajectory_with_column_segments_fp64(cfg1):
+@pytest.mark.parametrize("segments", [4, 8])
+def test_trajectory_with_column_segments_fp64(cfg1, segments):
     need_gpu()
     kw = dict(R=10, T=40, seed=SEED1, q_mode=1, q_fixed=8)
-    s = make_solver(cfg1, segments=4, **kw)
+    s = make_solver(cfg1, segments=segments, **kw)
     s.run()
     lg = s.log()
     ref = oracle_run(cfg1, **kw)
@@ -338,16 +345,18 @@ def test_validation_errors_on_device():
     assert e.value.status == SCG_ESTATE
 
 
+@pytest.mark.parametrize("segments", [0, 8])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
 @pytest.mark.parametrize("which", ["cfg1", "star", "pm1"])
-def test_rounding_matches_oracle_on_same_reconstruction(which, precision, tol, cfg1):
+def test_rounding_matches_oracle_on_same_reconstruction(which, precision, tol, segments, cfg1):
     """MaxCut rounding (Section 7.2): the same U gives the same R cut weights,
-    the same heaviest cut and bit-identical indicators."""
+    the same heaviest cut and bit-identical indicators (also with the matrix
+    stored in eight column segments)."""
     need_gpu()
     from oracle import round_maxcut, cut_indicators
     inst = {"cfg1": lambda: cfg1, "star": lambda: _star_plus(5000, 3),
             "pm1": lambda: synth.laplacian_instance(synth.torus_longrange(64, 5))}[which]()
-    s = make_solver(inst, R=6, T=60, seed=SEED1, q_mode=1, q_fixed=12, precision=precision)
+    s = make_solver(inst, R=6, T=60, seed=SEED1, q_mode=1, q_fixed=12, precision=precision, segments=segments)
     s.run()
     U, lam, err = s.reconstruct()
     w, best, chi = s.round_cut(U)
