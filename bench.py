@@ -79,8 +79,11 @@ KERNEL_SOURCES = ["scg_kernels.hpp", "scg_device.hpp", "scg_internal.hpp"]
 
 
 def spmv_kernel_name(summ: dict) -> str:
-    """The product kernel the autotuner chose: lanes 1 is the quad-chunk layout."""
-    return "k_spmvq" if summ["spmv_lanes"] == 1 else "k_spmv"
+    """The product kernel the autotuner chose: lanes 1 is the quad-chunk layout; with 8 column segments the
+    row-block kernel runs them in one launch and k_xcombine adds the segment sums."""
+    if summ["spmv_lanes"] == 1:
+        return "k_spmvq"
+    return "k_spmv + k_xcombine" if summ["spmv_segments"] == 8 else "k_spmv"
 
 
 def kernel_source_sha() -> str:
