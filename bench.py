@@ -50,13 +50,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # SpMV shapes whose HBM traffic the profile records: (lanes per row, workgroups cap, column segments);
-# workgroups 0 = one row-block range per wave; lanes 1 = the quad-chunk product (k_spmvq)
+# workgroups 0 = one row-block range per wave; lanes 1 = the quad-chunk product (k_spmvq); 8 segments = the
+# concurrent form (k_spmv slice sums + k_xcombine)
 PROBE_SHAPES = {
     2: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2), (1, 1536, 1), (1, 2048, 1)),
+    3: ((2, 1024, 8), (2, 2048, 8), (4, 1536, 4), (4, 0, 1)),
     5: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)),
 }
 TRAFFIC_FILES = {
     2: os.path.join(ROOT, "profiles", "spmv_traffic_torus_1m_fp32.json"),
+    3: os.path.join(ROOT, "profiles", "spmv_traffic_powerlaw_4m_fp32.json"),
     5: os.path.join(ROOT, "profiles", "spmv_traffic_geometric_8m_fp32.json"),
 }
 
@@ -196,36 +199,44 @@ def timed(solve: Solve, steps: int, warmup: int, torch):
 
 
 def cpu_baseline(inst, T: int, seconds: float = 15.0):
-    """The FP64 oracle on a bounded prefix of the workload, single-threaded."""
-    from threadpoolctl import threadpool_limits
+    """The FP64 oracle in its C/OpenMP form (oracle/c, checked against the Python oracle by the CPU tests) on a
+    bounded prefix of the workload: first on every host core the process may use, then on one thread, about
+    seconds / 2 each; each rate is extrapolated over the whole Lanczos schedule by operator applications."""
     import oracle
-    from oracle.sketchycgal import sketchy_cgal, state_of, gaussian_test_matrix
+    from oracle.c_oracle import MaxCutIterations
+    from oracle.sketchycgal import gaussian_test_matrix
     import synth
 
     qs = q_schedule(T, inst.n)
     Cm = inst.to_scipy()
     prm = oracle.OracleParams(R=10, T=T, seed=synth.CONFIG_SEEDS[2])
     Om = gaussian_test_matrix(inst.n, 10, prm.seed)      # drawn once, outside the timing
-    done_iters, spent, st = 0, 0.0, None
-    with threadpool_limits(limits=1):
-        while spent < seconds and done_iters < T:
-            t0 = time.perf_counter()
-            res = sketchy_cgal(Cm, inst.b, prm, Omega=Om, state0=st, t_stop=done_iters + 1)
-            spent += time.perf_counter() - t0
-            st = state_of(res, done_iters + 2)
-            done_iters += 1
-    work_done = sum(q + 1 for q in qs[:done_iters])
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     work_all = sum(q + 1 for q in qs)
-    full_time = spent / work_done * work_all
+    rates = {}
+    for threads in (cores, 1):
+        c = MaxCutIterations(Cm, inst.b, prm, Omega=Om)
+        done, spent = 0, 0.0
+        while spent < seconds / 2 and done < T:
+            t0 = time.perf_counter()
+            c.run(1, threads=threads)
+            spent += time.perf_counter() - t0
+            done += 1
+        work_done = sum(q + 1 for q in qs[:done])
+        rates[threads] = (T / (spent / work_done * work_all), done, spent, work_done)
+    v, done, spent, wd = rates[cores]
+    v1, done1, spent1, wd1 = rates[1]
     return {
-        "value": T / full_time,
+        "value": v,
         "unit": "CGAL iters/s",
-        "cores": 1,
-        "host_cpus": os.cpu_count(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"first {done_iters} of {T} iterations ({work_done} operator applications incl. the objective "
-                   f"product) in {spent:.1f} s, FP64, scipy CSR products, one thread; extrapolated over the whole "
-                   f"schedule ({work_all} applications)"),
+        "sample": (f"first {done} of {T} iterations ({wd} operator applications incl. the objective product) in "
+                   f"{spent:.1f} s on {cores} OpenMP threads, FP64, the C form of the oracle; extrapolated over the "
+                   f"whole schedule ({work_all} applications)"),
+        "single_thread_value": v1,
+        "single_thread_sample": f"first {done1} iterations in {spent1:.1f} s on one thread, extrapolated the same way",
+        "host_cpus": os.cpu_count(),
     }
 
 

@@ -81,9 +81,12 @@ typedef struct {
                                magnitude (columns only, sign in bit 31); 1: always store values */
     int32_t  autotune;      /* 1: time the SpMV variants (lanes per row, column segments, grid
                                size, and the quad-chunk product when the matrix qualifies) at
-                               init on the product of Lanczos step 1, and keep the fastest;
-                               runs when the matrix has at least 2^20 off-diagonal entries or
-                               segments is set                                                */
+                               init on the product of Lanczos step 1, and keep the fastest (in
+                               a fixed order; a later candidate must be at least 3% faster to
+                               replace an earlier one); runs when the matrix has at least 2^20
+                               off-diagonal entries or segments is set.  The chosen shape is
+                               reported by sketchycgal_summary and can be forced with
+                               segments, spmv_lanes and spmv_grid                             */
     int32_t  segments;      /* column segments of the SpMV: 0 = chosen by the autotuner
                                (1 below 1M nonzeros), or 1, 2, 4 (one launch per segment,
                                each adding into the product), or 8 (all eight in one launch,

@@ -710,6 +710,9 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
     const double mean = c->n > 0 ? (double)c->nnz_off / (double)c->n : 1.0;
     float best = 1e30f;
     int best_l = c->lanes, best_s = 1, best_g = 0;
+    // candidates are tried in a fixed order and a later one replaces the best only
+    // when it is at least 3% faster, so near-ties do not flip between runs
+    auto better = [&](float ms) { return ms < best * 0.97f; };
     // average of five launches after one warm-up, HIP events on the context stream
     auto time_lanes = [&](int l, float& ms) -> hipError_t {
         launch_spmv<T, SPMV_LANCZOS>(c, x1, 1, l);
@@ -741,7 +744,7 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
                 if (c->prm.spmv_lanes == 0 && l > 4 * mean + 4) break;
                 float ms = 0.f;
                 HIP_TRY(time_lanes(l, ms));
-                if (ms < best) { best = ms; best_l = l; best_s = nseg; best_g = gcap; }
+                if (better(ms)) { best = ms; best_l = l; best_s = nseg; best_g = gcap; }
             }
         }
         c->Gs = g_nat;
@@ -760,7 +763,7 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
                 if (c->prm.spmv_lanes > 0 && l != c->prm.spmv_lanes) continue;
                 float ms = 0.f;
                 HIP_TRY(time_lanes(l, ms));
-                if (ms < best) { best = ms; best_l = l; best_s = kSegMax; best_g = g; best_x = true; }
+                if (better(ms)) { best = ms; best_l = l; best_s = kSegMax; best_g = g; best_x = true; }
             }
         }
         c->xseg = false;
@@ -774,7 +777,7 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
             c->Gs = g;
             float ms = 0.f;
             HIP_TRY(time_lanes(1, ms));
-            if (ms < best) { best = ms; best_l = 1; best_s = 1; best_g = g; }
+            if (better(ms)) { best = ms; best_l = 1; best_s = 1; best_g = g; }
         }
         c->Gs = g_keep;
     }

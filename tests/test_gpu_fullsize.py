@@ -48,16 +48,7 @@ def _instance(k):
     return _cache[k]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("k", [2, 5, 3])
-def test_operator_at_full_size_within_rounding_bound(k, precision):
-    need_gpu()
-    inst = _instance(k)
-    announce(f"operator parity workload {k} n={inst.n} nnz={inst.nnz} {precision}")
-    s = make_solver(inst, R=10, T=5, seed=synth.CONFIG_SEEDS[k], precision=precision)
-    summ = s.summary()
-    announce(f"shape lanes={summ['spmv_lanes']} segments={summ['spmv_segments']} grid={summ['spmv_grid']} "
-             f"format={summ['matrix_format']}")
+def _check_operator(inst, s, precision):
     x = np.random.default_rng(11).standard_normal(inst.n)
     y = s.apply(x).cpu().numpy()
     Cs, bs, _, _ = scale_problem(inst.to_scipy(), inst.b, float(inst.n))
@@ -71,6 +62,40 @@ def test_operator_at_full_size_within_rounding_bound(k, precision):
     u = 2.0 ** -24 if precision == "fp32" else 2.0 ** -53
     ratio = np.abs(y - ref) / ((m + 10.0) * u * mag + 1e-300)
     assert np.max(ratio) <= 1.0, (np.max(ratio), int(np.argmax(ratio)))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("k", [2, 5, 3])
+def test_operator_at_full_size_within_rounding_bound(k, precision):
+    need_gpu()
+    inst = _instance(k)
+    announce(f"operator parity workload {k} n={inst.n} nnz={inst.nnz} {precision}")
+    s = make_solver(inst, R=10, T=5, seed=synth.CONFIG_SEEDS[k], precision=precision)
+    summ = s.summary()
+    announce(f"shape lanes={summ['spmv_lanes']} segments={summ['spmv_segments']} grid={summ['spmv_grid']} "
+             f"format={summ['matrix_format']}")
+    _check_operator(inst, s, precision)
+
+
+# every product family the autotuner picks between on these workloads, forced:
+# the quad-chunk product (torus), the row-block product with one or four
+# sequential column segments, and the eight concurrent segments (power law)
+FORCED = [(2, dict(spmv_lanes=1, spmv_grid=2048)), (2, dict(spmv_lanes=2, segments=1)),
+          (5, dict(spmv_lanes=2, segments=1, spmv_grid=1024)), (5, dict(spmv_lanes=2, segments=8, spmv_grid=1024)),
+          (3, dict(spmv_lanes=2, segments=8, spmv_grid=1024)), (3, dict(spmv_lanes=4, segments=4, spmv_grid=1536))]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("k,shape", FORCED)
+def test_operator_at_full_size_forced_shapes(k, shape, precision):
+    need_gpu()
+    inst = _instance(k)
+    announce(f"operator parity workload {k} {shape} {precision}")
+    s = make_solver(inst, R=10, T=5, seed=synth.CONFIG_SEEDS[k], precision=precision, autotune=0, **shape)
+    summ = s.summary()
+    assert summ["spmv_lanes"] == shape["spmv_lanes"]
+    assert summ["spmv_segments"] == shape.get("segments", 1)
+    _check_operator(inst, s, precision)
 
 
 def _invariants(g):
