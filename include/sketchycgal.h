@@ -124,6 +124,17 @@ typedef struct {
                                ball ||diag X - b|| <= r (the norm-constraint example of
                                Appendix D.3), r from sketchycgal_set_ball (until then 0).
                                Singleton engine only                                          */
+    int32_t  batch_kernel;  /* batched engine only (0 for the single-problem engine): the
+                               iteration kernel.  0 = chosen at init: with autotune = 1 every
+                               form that fits is timed on one iteration (after a warm-up one)
+                               and the fastest kept, in the order 1, 2, 3, a later form only
+                               when at least 3% faster; with autotune = 0 the first that fits;
+                               1 = the vector being multiplied held whole in LDS (it fits when
+                               the largest problem's vector and slice table do); 2 = held in
+                               LDS one column tile of half the largest vector at a time, each
+                               product making one pass over the slices per tile; 3 = products
+                               gathering from global memory.  A form that does not fit gives
+                               SCG_EINVAL                                                    */
 } scg_params;
 
 /* One record per iteration t, in scaled units (see file comment).  Gap and
@@ -157,6 +168,8 @@ typedef struct {
     int32_t matrix_format;    /* storage of the off-diagonal values: 0 values, 1 columns only
                                  (common value), 2 columns with sign bit (common magnitude)  */
     int32_t spmv_grid;        /* workgroups of the SpMV launch                                 */
+    int32_t batch_kernel;     /* batched engine: the iteration kernel form in use (1, 2, 3);
+                                 0 for the single-problem engine                              */
 } scg_summary;
 
 typedef struct scg_ctx scg_ctx;
@@ -208,7 +221,13 @@ scg_status sketchycgal_set_ball(scg_ctx* ctx, double radius);
 
 /* Enqueue `iters` iterations of alg:sketchy-cgal (loop body: ApproxMinEvec by
  * randomized Lanczos, z, y and sketch updates).  Asynchronous: never
- * synchronises.  SCG_ESTATE if it would run past T. */
+ * synchronises.  SCG_ESTATE if it would run past T.
+ * On a non-null stream (and constraint_set != 2) runs of iterations with the
+ * same Lanczos step count q_t replay a HIP graph captured once per q (the
+ * kernels read the iteration counter from device memory, advanced by the
+ * graph's last node); on the null stream the kernels are launched one by one.
+ * Both give bit-identical results.  The graphs are owned by the context and
+ * freed by sketchycgal_destroy. */
 scg_status sketchycgal_step(scg_ctx* ctx, int32_t iters);
 
 /* NystromSketch.Reconstruct (alg:nystrom-sketch-supp) of the current sketch,

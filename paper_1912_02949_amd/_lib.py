@@ -19,7 +19,7 @@ class scg_params(C.Structure):
         ("precision", C.c_int32), ("instance", C.c_int32), ("matrix_format", C.c_int32),
         ("autotune", C.c_int32), ("segments", C.c_int32), ("spmv_lanes", C.c_int32), ("spmv_grid", C.c_int32),
         ("basis_mode", C.c_int32), ("omega_mode", C.c_int32), ("trace_mode", C.c_int32),
-        ("constraint_set", C.c_int32),
+        ("constraint_set", C.c_int32), ("batch_kernel", C.c_int32),
     ]
 
 
@@ -38,6 +38,7 @@ class scg_summary(C.Structure):
         ("infeasibility", C.c_double), ("p_scaled", C.c_double), ("tau_scaled", C.c_double),
         ("c_F", C.c_double), ("alpha", C.c_double), ("alpha_scaled", C.c_double),
         ("spmv_lanes", C.c_int32), ("spmv_segments", C.c_int32), ("matrix_format", C.c_int32), ("spmv_grid", C.c_int32),
+        ("batch_kernel", C.c_int32),
     ]
 
 

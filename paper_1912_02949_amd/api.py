@@ -41,6 +41,7 @@ class Params:
     omega_mode: int = 0           # 0: store the test matrix; 1: regenerate it from its counters
     trace_mode: int = 0           # 0: tr X = alpha; 1: tr X <= alpha
     constraint_set: int = 0       # 0: diag X = b; 1: lo <= diag X <= hi (set_constraints); 2: ball (set_ball)
+    batch_kernel: int = 0         # batched engine: 0 chosen at init, 1 vector in LDS, 2 two LDS tiles, 3 global
 
     def to_c(self) -> _lib.scg_params:
         p = _lib.scg_params()
@@ -51,6 +52,7 @@ class Params:
         p.spmv_lanes, p.spmv_grid = self.spmv_lanes, self.spmv_grid
         p.basis_mode, p.omega_mode = self.basis_mode, self.omega_mode
         p.trace_mode, p.constraint_set = self.trace_mode, self.constraint_set
+        p.batch_kernel = self.batch_kernel
         p.precision = {"fp64": _lib.SCG_FP64, "fp32": _lib.SCG_FP32_STREAM}[self.precision]
         return p
 

@@ -276,6 +276,7 @@ IterArgs iter_args(scg_ctx* c, int t) {
     it.K = c->prm.K;
     it.seed = c->prm.seed;
     it.instance = (uint64_t)c->prm.instance;
+    it.dev = 0;
     return it;
 }
 
@@ -307,9 +308,12 @@ void enqueue_update(scg_ctx* c, const Prob<T>& P, int i, int accum) {
     hipLaunchKernelGGL((k_reorth_apply<T>), g, b, 0, c->stream, P, i, j0);
 }
 
+// One iteration; with dev the kernels take t, beta and eta from the device
+// counter (the form captured into a graph and replayed for every t with the same q).
 template <typename T>
-void enqueue_iteration(scg_ctx* c, int t) {
-    const IterArgs it = iter_args(c, t);
+void enqueue_iteration(scg_ctx* c, int t, int dev = 0) {
+    IterArgs it = iter_args(c, t);
+    it.dev = dev;
     Prob<T> P = prob<T>(c);
     if (P.ball) enqueue_ball_norm<T>(c, it.beta);
     enqueue_prep<T>(c, it);
@@ -918,6 +922,51 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
     return SCG_OK;
 }
 
+// The captured iteration for Lanczos step count q (instantiated on first use).
+template <typename T>
+hipError_t graph_for(scg_ctx* c, int t, int q, hipGraphExec_t* out) {
+    auto f = c->graphs.find(q);
+    if (f != c->graphs.end()) {
+        *out = f->second;
+        return hipSuccess;
+    }
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    enqueue_iteration<T>(c, t, 1);
+    hipLaunchKernelGGL(k_advance_t, dim3(1), dim3(1), 0, c->stream, c->sc);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    c->graphs[q] = ge;
+    *out = ge;
+    return hipSuccess;
+}
+
+// Runs of iterations with the same q_t replay one captured iteration, after a
+// one-thread kernel has set the device counter to the run's first t.
+template <typename T>
+scg_status step_graphs(scg_ctx* c, int32_t iters) {
+    int k = 0;
+    while (k < iters) {
+        const int t = c->t_next;
+        const int q = q_for(c->prm, c->n, t);
+        int m = 1;
+        while (k + m < iters && q_for(c->prm, c->n, t + m) == q) ++m;
+        hipGraphExec_t ge = nullptr;
+        HIP_TRY(graph_for<T>(c, t, q, &ge));
+        hipLaunchKernelGGL(k_set_t, dim3(1), dim3(1), 0, c->stream, c->sc, t);
+        HIP_TRY(hipGetLastError());
+        for (int j = 0; j < m; ++j) HIP_TRY(hipGraphLaunch(ge, c->stream));
+        c->t_next += m;
+        k += m;
+    }
+    return SCG_OK;
+}
+
 bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (!p || n < 1 || nnz < 0 || n >= INT32_MAX) return false;
     if (p->R < 1 || p->R > kRMax || p->R > n) return false;
@@ -939,6 +988,7 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (p->omega_mode != 0 && p->omega_mode != 1) return false;
     if (p->trace_mode != 0 && p->trace_mode != 1) return false;
     if (p->constraint_set < 0 || p->constraint_set > 2) return false;
+    if (p->batch_kernel != 0) return false;   // a batched-engine parameter
     return true;
 }
 
@@ -1045,6 +1095,11 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
 scg_status sketchycgal_step(scg_ctx* c, int32_t iters) {
     if (!c || iters < 0) return SCG_EINVAL;
     if ((int64_t)c->t_next - 1 + iters > c->prm.T) return SCG_ESTATE;
+    // on a non-null stream whole iterations are replayed from captured graphs
+    // (not with the ball constraint set, whose norm passes take beta by value)
+    if (c->stream != nullptr && c->prm.constraint_set != 2 && iters > 0) {
+        return (c->prm.precision == SCG_FP32_STREAM) ? step_graphs<float>(c, iters) : step_graphs<double>(c, iters);
+    }
     for (int k = 0; k < iters; ++k) {
         if (c->prm.precision == SCG_FP32_STREAM) enqueue_iteration<float>(c, c->t_next);
         else enqueue_iteration<double>(c, c->t_next);
@@ -1226,6 +1281,7 @@ scg_status sketchycgal_reconstruct(scg_ctx* c, double* U, double* lambda, double
 void sketchycgal_destroy(scg_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     delete c;
 }
 

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 #include "scg_device.hpp"
@@ -101,6 +102,7 @@ struct BatchArgs {
     const CT* scol;         // slice entries: pair p of lane l at offset + 2 (64 p + l)
     const T* sval;
     int desc_lds_off;       // byte offset of the slice table in dynamic LDS
+    int tile;               // columns per LDS tile of the two-tile kernel (a multiple of 64)
     int T_iters;
     int R;
     int reorth;             // 2: Gram-Schmidt pass against the whole basis
@@ -169,6 +171,19 @@ template <typename T, typename CT, int FMT>
 __device__ __forceinline__ T nz(CT cw, const T* val, int e, const T* x) {
     return nzv<T, CT, FMT>(cw, (FMT == FMT_VAL) ? val[e] : (T)0, x);
 }
+// The same term with x held as the column tile [lo, hi) (x[c - lo]); entries
+// of other columns, and the padding index n (hi <= n), contribute 0.  TL =
+// false is nzv itself.
+template <typename T, typename CT, int FMT, bool TL>
+__device__ __forceinline__ T nzt(CT cw, T vv, const T* x, int lo, int hi) {
+    if (!TL) return nzv<T, CT, FMT>(cw, vv, x);
+    const int c = (FMT == FMT_SGN) ? col_index(cw) : (int)cw;
+    if (c < lo || c >= hi) return (T)0;
+    const T xv = x[c - lo];
+    if (FMT == FMT_VAL) return vv * xv;
+    if (FMT == FMT_PAT) return xv;
+    return col_neg(cw) ? -xv : xv;
+}
 
 // sum_{e in row} C_e x_col(e), four nonzeros in flight per step.
 template <typename T, typename CT, int FMT>
@@ -206,10 +221,13 @@ template <> struct PairV<double> { using type = double2; };
 // (their entries, rows, shifts and, for the objective, diagonals) are loaded
 // before any is consumed.  `fin(p, row, a, shift, diag)` receives each row's
 // off-diagonal sum (without the common value of the compressed formats).
-template <typename T, typename CT, int FMT, bool OBJ, typename Fin>
+// With TL, xl holds only the columns [lo, hi) of the vector (at xl[c - lo])
+// and the sums are those of the tile's columns.
+template <typename T, typename CT, int FMT, bool OBJ, bool TL = false, typename Fin>
 __device__ __forceinline__ void sell_product(const int2* desc, int nsl, int nshort, int n, const int32_t* perm,
                                              const T* sp, const double* dCp, const CT* scol, const T* sval,
-                                             const int32_t* rp, const CT* col, const T* val, const T* xl, Fin fin) {
+                                             const int32_t* rp, const CT* col, const T* val, const T* xl, Fin fin,
+                                             int lo = 0, int hi = 0) {
     using PW = typename PairW<CT>::type;
     using PV = typename PairV<T>::type;
     constexpr int PF = (sizeof(CT) == 2 && FMT != FMT_VAL) ? 6 : 4;   // pairs loaded ahead per slice
@@ -248,7 +266,8 @@ __device__ __forceinline__ void sell_product(const int2* desc, int nsl, int nsho
                 if (2 * pp < d[g].y) {
                     const T v0 = (FMT == FMT_VAL) ? (T)vw[g][pp].x : (T)0;
                     const T v1 = (FMT == FMT_VAL) ? (T)vw[g][pp].y : (T)0;
-                    a += nzv<T, CT, FMT>((CT)pair_lo(cw[g][pp]), v0, xl) + nzv<T, CT, FMT>((CT)pair_hi(cw[g][pp]), v1, xl);
+                    a += nzt<T, CT, FMT, TL>((CT)pair_lo(cw[g][pp]), v0, xl, lo, hi) +
+                         nzt<T, CT, FMT, TL>((CT)pair_hi(cw[g][pp]), v1, xl, lo, hi);
                 }
             }
             for (int pp = PF; 2 * pp < d[g].y; ++pp) {   // wide slices
@@ -260,7 +279,7 @@ __device__ __forceinline__ void sell_product(const int2* desc, int nsl, int nsho
                     v0 = vv.x;
                     v1 = vv.y;
                 }
-                a += nzv<T, CT, FMT>((CT)pair_lo(w), v0, xl) + nzv<T, CT, FMT>((CT)pair_hi(w), v1, xl);
+                a += nzt<T, CT, FMT, TL>((CT)pair_lo(w), v0, xl, lo, hi) + nzt<T, CT, FMT, TL>((CT)pair_hi(w), v1, xl, lo, hi);
             }
             if (row[g] >= 0) fin((kb + g * kBW) * 64 + lane, row[g], (double)a, (double)sv[g], dg[g]);
         }
@@ -270,7 +289,8 @@ __device__ __forceinline__ void sell_product(const int2* desc, int nsl, int nsho
         const int r = perm[p];
         const int e0 = rp[r], e1 = rp[r + 1];
         T a = 0;
-        for (int e = e0 + lane; e < e1; e += 64) a += nz<T, CT, FMT>(col[e], val, e, xl);
+        for (int e = e0 + lane; e < e1; e += 64)
+            a += nzt<T, CT, FMT, TL>(col[e], (FMT == FMT_VAL) ? val[e] : (T)0, xl, lo, hi);
         const double tot = wave_sum((double)a);
         if (lane == 0) fin(p, r, tot, (double)sp[p], OBJ ? dCp[p] : 0.0);
     }
@@ -428,8 +448,16 @@ __device__ __forceinline__ void prep_shift(const BatchArgs<T, CT>& A, const Batc
 // slices of 64 rows (rows sorted by length, padded to the slice's even
 // width); only the products use that order, every vector stays in row order.
 // Row loops move 4 consecutive entries per thread with 16-byte accesses.
-template <typename T, typename CT, int FMT, int RB>
+//
+// NT = 2 is the form for batches whose largest vector does not fit the LDS
+// budget: LDS holds one column tile of A.tile entries at a time; each product
+// runs twice over the slices, once per tile of the vector (loaded from its
+// global copy, the Lanczos basis or the Ritz vector), the first pass storing
+// its row sums in u and the second adding them; the update, the Ritz vector
+// and the tail read the vectors from global memory.
+template <typename T, typename CT, int FMT, int RB, int NT>
 __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
+    constexpr bool TL = (NT > 1);
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     __shared__ double red[kRedMax * kBW];
     __shared__ double so[SO_N];
@@ -457,14 +485,46 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
     const double* dCp = A.dC_pos + D.pos0;
     T* u = A.u + D.pos0;
     T* V = A.V + D.off_V;
+    T* vg = A.v + D.pos0;   // the Ritz vector's global copy (two-tile form)
     const T* Om = A.Om + D.off_OS;
+    const int h = TL ? A.tile : n;
     for (int kk = tid; kk < nsl; kk += kBT) desc[kk] = A.sdesc[D.sl0 + kk];
-    if (tid == 0) xl[n] = (T)0;
+    if (!TL && tid == 0) xl[n] = (T)0;
 
     prep_shift<T, CT>(A, D, t, beta, [&](int r, int m, double (&g)[4]) {
         st4(V + r, m, g);   // rounds g to the stored type
-        for (int j = 0; j < m; ++j) xl[r + j] = (T)g[j];
+        if (!TL)
+            for (int j = 0; j < m; ++j) xl[r + j] = (T)g[j];
     }, red, so);
+    // off-diagonal row sums of the vector xg (its LDS copy in the one-tile form):
+    // fin(p, r, a, shift, diag) gets each row's complete sum
+    auto product = [&](auto obj_tag, const T* xg, auto fin) {
+        constexpr bool OBJ = decltype(obj_tag)::value;
+        if constexpr (!TL) {
+            sell_product<T, CT, FMT, OBJ>(desc, nsl, nshort, n, perm, sp, dCp, A.scol, A.sval, rp, A.col, A.val,
+                                          xl, fin);
+        } else {
+            for (int lo = 0; lo < n; lo += h) {
+                const int hi = (lo + h < n) ? lo + h : n;
+                __syncthreads();   // the previous tile's readers are done
+                for (int r = tid; r < hi - lo; r += kBT) xl[r] = xg[lo + r];
+                __syncthreads();
+                const bool first = (lo == 0), last = (hi == n);
+                sell_product<T, CT, FMT, OBJ, true>(
+                    desc, nsl, nshort, n, perm, sp, dCp, A.scol, A.sval, rp, A.col, A.val, xl,
+                    [&](int p, int r, double a, double sv, double dg) {
+                        // the same thread handles row r in every tile
+                        if (!first) a += (double)u[r];
+                        if (!last) {
+                            u[r] = (T)a;
+                            return;
+                        }
+                        fin(p, r, a, sv, dg);
+                    },
+                    lo, hi);
+            }
+        }
+    };
     // the shift in position order, for the products
     for (int qd = tid; 4 * qd < n; qd += kBT) {
         const int m = quad_m(qd, n), p = 4 * qd;
@@ -484,13 +544,13 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
     for (int i = 0; i < q; ++i) {
         const double xs = s_inv[i];
         double acc[1] = {0.0};
-        sell_product<T, CT, FMT, false>(desc, nsl, nshort, n, perm, sp, dCp, A.scol, A.sval, rp, A.col, A.val, xl,
-                                        [&](int, int r, double a, double sv, double) {
-                                            const double xr = (double)xl[r];
-                                            const T ut = (T)((a * cv + sv * xr) * xs);
-                                            u[r] = ut;
-                                            acc[0] += xr * xs * (double)ut;
-                                        });
+        const T* vi = V + (size_t)i * ld;
+        product(std::false_type{}, vi, [&](int, int r, double a, double sv, double) {
+            const double xr = TL ? (double)vi[r] : (double)xl[r];
+            const T ut = (T)((a * cv + sv * xr) * xs);
+            u[r] = ut;
+            acc[0] += xr * xs * (double)ut;
+        });
         breduce<1>(acc, red, so + SO_OM);
         const double om = so[SO_OM];
         if (tid == 0) {
@@ -505,29 +565,31 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
         double acc2[1] = {0.0};
         for (int qb = tid; 4 * qb < n; qb += 2 * kBT) {
             int mq[2];
-            double uu[2][4], mm[2][4];
+            double uu[2][4], mm[2][4], xx[2][4];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int qd = qb + h * kBT;
-                mq[h] = quad_m(qd, n);
-                if (mq[h] > 0) {
-                    ld4(u + 4 * qd, mq[h], uu[h]);
-                    ld4(vm + 4 * qd, mq[h], mm[h]);
+            for (int hh = 0; hh < 2; ++hh) {
+                const int qd = qb + hh * kBT;
+                mq[hh] = quad_m(qd, n);
+                if (mq[hh] > 0) {
+                    ld4(u + 4 * qd, mq[hh], uu[hh]);
+                    ld4(vm + 4 * qd, mq[hh], mm[hh]);
+                    if (TL) ld4(vi + 4 * qd, mq[hh], xx[hh]);
                 }
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (mq[h] > 0) {
-                    const int r = 4 * (qb + h * kBT);
+            for (int hh = 0; hh < 2; ++hh) {
+                if (mq[hh] > 0) {
+                    const int r = 4 * (qb + hh * kBT);
                     double w4[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        w4[j] = (j < mq[h]) ? uu[h][j] - c1 * (double)xl[r + j] - c2 * mm[h][j] : 0.0;
-                    st4(w + r, mq[h], w4);   // rounds w4 to the stored type
+                        w4[j] = (j < mq[hh]) ? uu[hh][j] - c1 * (TL ? xx[hh][j] : (double)xl[r + j]) - c2 * mm[hh][j]
+                                             : 0.0;
+                    st4(w + r, mq[hh], w4);   // rounds w4 to the stored type
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (j < mq[h]) {
-                            xl[r + j] = (T)w4[j];   // own rows: no other thread reads them before the barrier
+                        if (j < mq[hh]) {
+                            if (!TL) xl[r + j] = (T)w4[j];   // own rows: no other thread reads them before the barrier
                             acc2[0] += w4[j] * w4[j];
                         }
                 }
@@ -556,7 +618,7 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
                 for (int j = j0; j <= i; ++j) a += (s_h[j] * s_inv[j]) * s_inv[j] * (double)V[(size_t)j * ld + p];
                 const T wt = (T)((double)w[p] - a);
                 w[p] = wt;
-                xl[p] = wt;
+                if (!TL) xl[p] = wt;
                 acc2[0] += (double)wt * (double)wt;
             }
         }
@@ -610,12 +672,17 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             const int r = 4 * (qb0 + tid + h * kBT);
+            if (TL) {
+                if (mq[h] > 0) st4(vg + r, mq[h], a4[h]);   // rounds to the stored type
+            } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (j < mq[h]) xl[r + j] = (T)a4[h][j];
+                for (int j = 0; j < 4; ++j)
+                    if (j < mq[h]) xl[r + j] = (T)a4[h][j];
+            }
         }
     }
     __syncthreads();
+    auto vat = [&](int r) { return TL ? (double)vg[r] : (double)xl[r]; };
     // ||v||^2 and v^T Omega from the stored (rounded) vector
     {
         double racc[RB + 1];
@@ -626,7 +693,7 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
             double v4[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                v4[j] = (j < m) ? (double)xl[r + j] : 0.0;
+                v4[j] = (j < m) ? vat(r + j) : 0.0;
                 racc[0] += v4[j] * v4[j];
             }
 #pragma unroll
@@ -645,18 +712,16 @@ __global__ __launch_bounds__(kBT) void k_batch_sell(BatchArgs<T, CT> A) {
     // objective v_hat^T C v_hat and the eigen-residual ||D v_hat - xi v_hat||^2
     {
         double oa[2] = {0.0, 0.0};
-        sell_product<T, CT, FMT, true>(desc, nsl, nshort, n, perm, sp, dCp, A.scol, A.sval, rp, A.col, A.val, xl,
-                                       [&](int p, int r, double a, double sv, double dg) {
-                                           const double xr = (double)xl[r] * iv;
-                                           const double off = a * cv * iv;
-                                           const double rr = (off + sv * xr) - xi * xr;
-                                           oa[0] += xr * (off + dg * xr);
-                                           oa[1] += rr * rr;
-                                       });
+        product(std::true_type{}, vg, [&](int p, int r, double a, double sv, double dg) {
+            const double xr = vat(r) * iv;
+            const double off = a * cv * iv;
+            const double rr = (off + sv * xr) - xi * xr;
+            oa[0] += xr * (off + dg * xr);
+            oa[1] += rr * rr;
+        });
         breduce<2>(oa, red, so + SO_OBJ);
     }
-    iteration_tail<T, CT>(A, D, G, ii, t, q, k, xi, beta, eta, iv, vnorm2, [&](int r) { return (double)xl[r]; },
-                          red, so);
+    iteration_tail<T, CT>(A, D, G, ii, t, q, k, xi, beta, eta, iv, vnorm2, vat, red, so);
 }
 
 // The same iteration with the SpMV gathering from global memory (instances
@@ -1041,9 +1106,12 @@ struct scg_batch {
     hipStream_t stream;
     int fmt;
     bool col16;        // 16-bit column indices (every instance small enough)
-    bool xl;           // the multiplied vector kept in LDS (sliced-layout kernel)
-    size_t lds_bytes;  // dynamic LDS per workgroup when xl
-    int desc_lds_off;  // byte offset of the slice table in dynamic LDS
+    int xmode;            // iteration kernel: 1 vector in LDS, 2 in two LDS column tiles, 3 global gathers
+    bool fits[4];         // forms the LDS budget admits (form 3 always)
+    size_t lds_bytes[3];  // dynamic LDS per workgroup of forms 1 and 2
+    int desc_off[3];      // byte offset of the slice table in dynamic LDS, forms 1 and 2
+    int tile;             // columns per LDS tile of form 2 (a multiple of 64)
+    float form_ms[4];     // one timed iteration of each form tried at init (0: not timed)
     std::vector<BatchInst> hinst;
     std::vector<int64_t> row0;
     BatchInst* inst;
@@ -1098,7 +1166,8 @@ BatchArgs<T, CT> bargs(scg_batch* c) {
     A.sdesc = c->sdesc;
     A.scol = (const CT*)c->scol;
     A.sval = (const T*)c->sval;
-    A.desc_lds_off = c->desc_lds_off;
+    A.desc_lds_off = c->desc_off[c->xmode == 2 ? 2 : 1];
+    A.tile = c->tile;
     A.T_iters = c->prm.T;
     A.R = c->prm.R;
     A.reorth = c->prm.reorth;
@@ -1111,9 +1180,9 @@ BatchArgs<T, CT> bargs(scg_batch* c) {
 // Launch one iteration, or (prepare) raise the kernel's dynamic-LDS limit.
 template <typename T, typename CT, int FMT, int RB>
 hipError_t launch_leaf(scg_batch* c, bool prepare) {
-    if (c->xl) {
-        auto* kern = &k_batch_sell<T, CT, FMT, RB>;
-        const unsigned lds = (unsigned)c->lds_bytes;
+    if (c->xmode == 1 || c->xmode == 2) {
+        auto* kern = (c->xmode == 1) ? &k_batch_sell<T, CT, FMT, RB, 1> : &k_batch_sell<T, CT, FMT, RB, 2>;
+        const unsigned lds = (unsigned)c->lds_bytes[c->xmode];
         if (prepare) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(c->ninst), dim3(kBT), lds, c->stream, bargs<T, CT>(c));
     } else {
@@ -1280,14 +1349,23 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     }
     // column words: 16 bits when every local index, the padding index n and the sign bit fit
     c->col16 = (c->prm.matrix_format != 1) && (nmax <= ((c->fmt == FMT_SGN) ? 32767 : 65535));
-    // LDS path: the vector (plus the zero at index n) and the slice table fit the budget
+    // LDS forms: the whole vector (plus the zero at index n), or a column tile of
+    // half of the longest one, and the slice table within the budget
     {
         int64_t nslmax = 0;
         for (int k = 0; k < ninst; ++k) nslmax = std::max<int64_t>(nslmax, (c->hinst[k].n + 63) / 64);
-        const size_t xb = al256((size_t)(ldmax + 64) * sizeof(T));
-        c->desc_lds_off = (int)xb;
-        c->lds_bytes = xb + 8 * (size_t)nslmax;
-        c->xl = c->lds_bytes <= kLdsBudget;
+        const size_t xb1 = al256((size_t)(ldmax + 64) * sizeof(T));
+        c->tile = (int)(((ldmax + 1) / 2 + 63) / 64 * 64);
+        const size_t xb2 = al256((size_t)c->tile * sizeof(T));
+        c->desc_off[1] = (int)xb1;
+        c->desc_off[2] = (int)xb2;
+        c->lds_bytes[1] = xb1 + 8 * (size_t)nslmax;
+        c->lds_bytes[2] = xb2 + 8 * (size_t)nslmax;
+        c->fits[1] = c->lds_bytes[1] <= kLdsBudget;
+        c->fits[2] = c->lds_bytes[2] <= kLdsBudget;
+        c->fits[3] = true;
+        const int f = c->prm.batch_kernel;
+        if (f != 0 && !c->fits[f]) return SCG_EINVAL;   // a forced form that does not fit
     }
     std::vector<double> invc(ninst), inva(ninst);
     for (int k = 0; k < ninst; ++k) {
@@ -1338,7 +1416,7 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));   // dCraw / sumsq consumed
-    if (c->xl) {
+    if (c->fits[1] || c->fits[2]) {
         const scg_status st = c->col16 ? build_slices<T, uint16_t>(c, L, hrp_off) : build_slices<T, int32_t>(c, L, hrp_off);
         if (st != SCG_OK) return st;
     }
@@ -1355,17 +1433,61 @@ scg_status binit_typed(scg_batch* c, const BLayout& L, char* base, const int64_t
     HIP_TRY(hipMemcpyAsync(c->qtab, qtab.data(), 4 * qtab.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->order, order.data(), 4 * ninst, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->inst, c->hinst.data(), sizeof(BatchInst) * ninst, hipMemcpyHostToDevice, c->stream));
-    std::vector<BatchScal> hs(ninst);
-    std::memset(hs.data(), 0, sizeof(BatchScal) * ninst);
-    for (auto& x : hs) x.t_next = 1;
-    HIP_TRY(hipMemcpyAsync(c->scal, hs.data(), sizeof(BatchScal) * ninst, hipMemcpyHostToDevice, c->stream));
     const size_t es = (c->prm.precision == SCG_FP32_STREAM) ? 4 : 8;
-    HIP_TRY(hipMemsetAsync(c->z, 0, 8 * c->nvec, c->stream));
-    HIP_TRY(hipMemsetAsync(c->y, 0, 8 * c->nvec, c->stream));
-    HIP_TRY(hipMemsetAsync(c->S, 0, es * L.OStot, c->stream));
-    HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * ninst * c->prm.T, c->stream));
-    HIP_TRY(hipMemsetAsync(c->counter, 0, 256, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    // the state before iteration 1 (also after each form timed below)
+    auto reset_state = [&]() -> scg_status {
+        std::vector<BatchScal> hs(ninst);
+        std::memset(hs.data(), 0, sizeof(BatchScal) * ninst);
+        for (auto& x : hs) x.t_next = 1;
+        HIP_TRY(hipMemcpyAsync(c->scal, hs.data(), sizeof(BatchScal) * ninst, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemsetAsync(c->z, 0, 8 * c->nvec, c->stream));
+        HIP_TRY(hipMemsetAsync(c->y, 0, 8 * c->nvec, c->stream));
+        HIP_TRY(hipMemsetAsync(c->S, 0, es * L.OStot, c->stream));
+        HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * ninst * c->prm.T, c->stream));
+        HIP_TRY(hipMemsetAsync(c->counter, 0, 256, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return SCG_OK;
+    };
+    scg_status st = reset_state();
+    if (st != SCG_OK) return st;
+    // the iteration kernel: forced, the first form that fits, or the fastest on one
+    // iteration (after a warm-up iteration) in the order 1, 2, 3, a later form
+    // replacing an earlier one only when at least 3% faster
+    for (int f = 0; f < 4; ++f) c->form_ms[f] = 0.f;
+    if (c->prm.batch_kernel != 0) {
+        c->xmode = c->prm.batch_kernel;
+    } else {
+        c->xmode = c->fits[1] ? 1 : (c->fits[2] ? 2 : 3);
+        if (c->prm.autotune) {
+            hipEvent_t e0, e1;
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            float best = 1e30f;
+            int best_f = c->xmode;
+            for (int f = 1; f <= 3; ++f) {
+                if (!c->fits[f]) continue;
+                c->xmode = f;
+                HIP_TRY(enqueue_iter(c, true));
+                HIP_TRY(enqueue_iter(c));
+                if ((st = reset_state()) != SCG_OK) return st;
+                HIP_TRY(hipEventRecord(e0, c->stream));
+                HIP_TRY(enqueue_iter(c));
+                HIP_TRY(hipEventRecord(e1, c->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                c->form_ms[f] = ms;
+                if (ms < best * 0.97f) {
+                    best = ms;
+                    best_f = f;
+                }
+                if ((st = reset_state()) != SCG_OK) return st;
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            c->xmode = best_f;
+        }
+    }
     return SCG_OK;
 }
 
@@ -1379,6 +1501,7 @@ bool bparams_ok(const scg_params* p, int ninst, const int64_t* inst_n) {
     if (p->matrix_format != 0 && p->matrix_format != 1) return false;
     if (p->basis_mode != 0 || p->omega_mode != 0) return false;   // the batch keeps both in HBM
     if (p->trace_mode != 0 || p->constraint_set != 0) return false;   // the MaxCut model only
+    if (p->batch_kernel < 0 || p->batch_kernel > 3) return false;
     int64_t total = 0;
     for (int k = 0; k < ninst; ++k) {
         const int64_t n = inst_n[k];
@@ -1569,6 +1692,7 @@ scg_status sketchycgal_batch_summary(scg_batch* c, int32_t inst, scg_summary* o)
     o->infeasibility = I.alpha / I.alpha_s * infeas;
     o->matrix_format = c->fmt;
     o->spmv_grid = c->ninst;
+    o->batch_kernel = c->xmode;
     return (hs.flags & 2) ? SCG_ENUMERIC : SCG_OK;
 }
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+
 #include "../../include/sketchycgal.h"
 
 namespace scg {
@@ -40,6 +42,7 @@ struct DevScalars {
     int32_t k, done, flags, t_done;
     int32_t err;                               // init validation bits
     int32_t kr;                                // Lanczos steps of the current Ritz vector
+    int32_t t_iter;                            // iteration of a replayed graph (IterArgs.dev)
 };
 
 // Problem description passed by value to kernels.
@@ -153,6 +156,7 @@ struct scg_ctx {
     int2* qc;        // per chunk: (first row, quads used)
     int64_t nqc;     // chunks built (0: the matrix does not qualify)
     int64_t qc_cap;  // chunks reserved
+    std::map<int, hipGraphExec_t> graphs;   // one captured iteration per Lanczos step count q (non-null stream)
 };
 
 // Arguments of the FP64 Nystrom reconstruction of one sketch (column-major

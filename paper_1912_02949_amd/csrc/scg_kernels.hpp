@@ -48,7 +48,25 @@ struct IterArgs {
     double beta_next;     // beta_{t+1} = beta0 sqrt(t + 2), for the slack of the dual update
     uint64_t seed;
     uint64_t instance;
+    int dev;              // 1: t (and beta, eta, beta_next) from DevScalars::t_iter, as in a replayed graph
 };
+
+// The iteration's scalars, from the device counter when the launch belongs to
+// a captured graph (the same formulas as the host's iter_args).
+__device__ __forceinline__ IterArgs resolve_iter(IterArgs it, const DevScalars* sc) {
+    if (!it.dev) return it;
+    const int t = sc->t_iter;
+    it.t = t;
+    it.beta = it.beta0 * sqrt(t + 1.0);
+    it.beta_next = it.beta0 * sqrt(t + 2.0);
+    it.eta = 2.0 / (t + 1.0);
+    return it;
+}
+
+// Graph replays: set the device iteration counter before a run of replays, and
+// advance it as the last launch of each replayed iteration.
+__global__ void k_set_t(DevScalars* sc, int t) { sc->t_iter = t; }
+__global__ void k_advance_t(DevScalars* sc) { sc->t_iter += 1; }
 
 // Matrix entries move as 16-byte vectors.  They are loaded with the default
 // cache policy: a nontemporal hint on this stream measured 13% slower on the
@@ -942,6 +960,7 @@ __global__ __launch_bounds__(kBlock) void k_ball_norm(Prob<T> P, double beta) {
 // partial sums of ||z - w_bar||^2, ||y||^2 and y^T (z - w_bar).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ball_r2(Prob<T> P, IterArgs it) {
+    it = resolve_iter(it, P.sc);
     const int64_t n = P.n;
     const double cb = ball_factor(P);
     double a[3] = {0.0, 0.0, 0.0};
@@ -970,6 +989,7 @@ __global__ __launch_bounds__(kBlock) void k_ball_r2(Prob<T> P, IterArgs it) {
 // place of b (alg:full-sketchy-cgal-supp).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
+    it = resolve_iter(it, P.sc);
     DevScalars* sc = P.sc;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->done = 0;
@@ -1021,6 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(Prob<T> P, IterArgs it) {
 // for a box, (y^T y, y^T (z - w_bar) for the K guard) and dist_K(z)^2 (box).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_primal(Prob<T> P, IterArgs it) {
+    it = resolve_iter(it, P.sc);
     DevScalars* sc = P.sc;
     const double iv = sc->inv_vnorm;
     const bool hon = (P.trace_mode == 0) || (sc->xi < 0.0);
@@ -1081,6 +1102,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Prob<T> P, IterArgs it) {
 // S <- (1-eta) S + eta ha v_hat (v_hat^T Omega).
 template <typename T, int RB>
 __global__ __launch_bounds__(kBlock) void k_dual_sketch(Prob<T> P, IterArgs it) {
+    it = resolve_iter(it, P.sc);
     DevScalars* sc = P.sc;
     const int64_t n = P.n;
     const bool box = P.lo != nullptr;

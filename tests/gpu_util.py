@@ -34,7 +34,7 @@ def make_solver(inst: synth.MaxCutInstance, omega=None, **kw):
 def oracle_params(**kw) -> OracleParams:
     kw = dict(kw)
     for key in ("precision", "matrix_format", "segments", "autotune", "spmv_lanes", "spmv_grid",
-                "basis_mode", "omega_mode", "constraint_set"):
+                "basis_mode", "omega_mode", "constraint_set", "batch_kernel"):
         kw.pop(key, None)
     alpha = kw.pop("alpha", 0.0)
     op = OracleParams(**{k: v for k, v in kw.items() if k in {f.name for f in dataclasses.fields(OracleParams)}})

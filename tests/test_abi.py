@@ -57,7 +57,8 @@ def test_workspace_size_and_validation():
            dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=3), dict(reorth=-1), dict(precision=7), dict(n=0),
            dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_lanes=1, segments=2), dict(spmv_lanes=1, matrix_format=1), dict(spmv_grid=-1), dict(spmv_grid=4096),
            dict(q_mode=1, q_fixed=600, n=10_000), dict(basis_mode=2), dict(basis_mode=-1), dict(omega_mode=2),
-           dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=3), dict(constraint_set=-1)]
+           dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=3), dict(constraint_set=-1),
+               dict(batch_kernel=1)]
     for kw in bad:
         st, _ = _ws(**dict(kw))
         assert st == _lib.SCG_EINVAL, kw
@@ -158,7 +159,7 @@ def test_batch_workspace_size_and_validation():
     for sizes, kw in [([200, 5], {}), ([], {}), ([100], dict(reorth=3)), ([100], dict(T=0)),
                       ([1000], dict(q_mode=1, q_fixed=129)), ([100], dict(precision=3)), ([100], dict(R=33)),
                       ([100], dict(basis_mode=1)), ([100], dict(omega_mode=1)), ([100], dict(trace_mode=1)),
-                      ([100], dict(constraint_set=1))]:
+                      ([100], dict(constraint_set=1)), ([100], dict(batch_kernel=4)), ([100], dict(batch_kernel=-1))]:
         st, _ = _bws(sizes, **kw)
         assert st == _lib.SCG_EINVAL, (sizes, kw)
 

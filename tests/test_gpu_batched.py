@@ -302,3 +302,61 @@ def test_batched_rounding_matches_oracle_on_same_reconstruction(precision, tol):
         assert np.abs(w - w_ref).max() < tol * np.abs(w_ref).max(), i
         assert w_ref[best] >= w_ref[best_ref] - tol * abs(w_ref[best_ref]), i
         assert np.array_equal(chi.cpu().numpy(), cut_indicators(U.cpu().numpy())[:, best]), i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", [1, 2, 3])
+def test_batched_kernel_forms_trajectories(form, precision):
+    """Each iteration kernel form forced (1: the vector in LDS, 2: two LDS column
+    tiles, 3: gathers from global memory): FP64 trajectories against the oracle
+    at the trajectory bar, FP32 first iteration at its one-iteration bars."""
+    need_gpu()
+    insts = traj_batch()
+    T = 40 if precision == "fp64" else 1
+    kw = dict(R=8, T=T, seed=SEED4, q_mode=1, q_fixed=8, precision=precision)
+    bt = make_batch(insts, batch_kernel=form, **kw)
+    assert bt.summary(0)["batch_kernel"] == form
+    bt.run()
+    for i, inst in enumerate(insts):
+        ref = oracle_run(inst, instance=i, **kw)
+        lg = bt.log(i)
+        if precision == "fp64":
+            _check_trajectory(lg, ref, TRAJ_TOL, (form, i))
+            assert maxrel(bt.get_state(i)["z"].cpu().numpy(), ref.z) < Z_TOL, (form, i)
+        else:   # (the 9-cycle's FP32 recurrence need not break down where the FP64 one does)
+            assert rel(lg["p"][0], ref.log["p"][0]) < 1e-4, (form, i)
+            assert rel(lg["xi"][0], ref.log["xi"][0]) < 2e-2, (form, i)
+
+
+@pytest.mark.parametrize("form", [2, 3])
+def test_batched_kernel_forms_single_iteration_with_hub_rows(form):
+    """Forms 2 and 3 with a star (hub row summed by a whole wave, across both
+    column tiles) and valued members: one iteration from the oracle's state
+    with full reorthogonalisation, held to 1e-9 (S 1e-8)."""
+    need_gpu()
+    insts = valued_batch()
+    kw = dict(R=8, T=40, seed=SEED4, q_mode=1, q_fixed=36, reorth=2)
+    bt = make_batch(insts, batch_kernel=form, **kw)
+    t = 2
+    refs = []
+    for i, inst in enumerate(insts):
+        st = oracle_snapshots(inst, [t], instance=i, **kw)[t]
+        bt.set_state(i, t, st["z"], st["y"], st["S"], st["p"], st["tau"])
+        refs.append(sketchy_cgal(inst.to_scipy(), inst.b, oracle_params(instance=i, **kw), state0=st, t_stop=t))
+    bt.step(1)
+    for i, ref in enumerate(refs):
+        g = bt.get_state(i)
+        assert rel(g["p"], ref.p) < 1e-9, (form, i)
+        assert rel(bt.log(i)["infeas"][t - 1], ref.log["infeas"][-1]) < 1e-9, (form, i)
+        assert maxrel(g["z"].cpu().numpy(), ref.z) < 1e-9, (form, i)
+        assert maxrel(g["S"].cpu().numpy(), ref.S) < 1e-8, (form, i)
+
+
+def test_batched_kernel_forced_form_that_does_not_fit():
+    """The whole-vector LDS form cannot hold an FP64 vector of 20 000 entries."""
+    need_gpu()
+    from paper_1912_02949_amd._lib import SCGError, SCG_EINVAL
+    big = synth.laplacian_instance(synth.erdos_renyi(20000, 80000, 3))
+    with pytest.raises(SCGError) as e:
+        make_batch([big], R=8, T=2, seed=SEED4, precision="fp64", batch_kernel=1)
+    assert e.value.status == SCG_EINVAL

@@ -181,20 +181,24 @@ def test_torus_two_iterations_full_reorth_at_full_size(precision):
         assert maxrel(g["y"].cpu().numpy(), ref.y) < 1e-9
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batched_workload_at_full_size(precision):
-    # the 256-problem batch of the benchmark in its launch configuration; the
-    # largest, the median and the smallest problem against the oracle run on it
-    # alone.  FP64, two iterations: the oracle's own floor on these three
-    # (reversed row sums) is <= 1.2e-9 on p and ||z - b||, 2.6e-9 on z; bars
-    # at about 100x.  FP32-stream: its one-iteration floor.
+@pytest.mark.parametrize("precision,form", [("fp64", 0), ("fp32", 0), ("fp64", 2), ("fp64", 3), ("fp32", 1)])
+def test_batched_workload_at_full_size(precision, form):
+    # the 256-problem batch of the benchmark in its launch configuration (form 0:
+    # the kernel form the autotuner picks), and each form forced; the largest,
+    # the median and the smallest problem against the oracle run on it alone.
+    # FP64, two iterations: the oracle's own floor on these three (reversed row
+    # sums) is <= 1.2e-9 on p and ||z - b||, 2.6e-9 on z; bars at about 100x.
+    # FP32-stream: its one-iteration floor.
     need_gpu()
     from paper_1912_02949_amd import BatchedSketchyCGAL, Params
     insts = synth.batched_erdos_renyi(256, 200, 20000, 8)
     T = 2 if precision == "fp64" else 1
     kw = dict(R=8, T=T, seed=synth.CONFIG_SEEDS[4], precision=precision)
-    announce(f"batched workload at full size {precision}")
-    bt = BatchedSketchyCGAL(insts, Params(**kw))
+    announce(f"batched workload at full size {precision} form {form}")
+    bt = BatchedSketchyCGAL(insts, Params(batch_kernel=form, **kw))
+    used = bt.summary(0)["batch_kernel"]
+    announce(f"batched kernel form {used}")
+    assert used == form or (form == 0 and used in (1, 2, 3))
     bt.run()
     order = np.argsort([g.n for g in insts])
     for i in (int(order[-1]), int(order[len(order) // 2]), int(order[0])):

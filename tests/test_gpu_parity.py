@@ -379,3 +379,43 @@ def test_gpu_solve_reconstruct_round_finds_the_max_cut(graph, opt):
     assert w[best] == pytest.approx(opt, abs=1e-9)
     x = chi.cpu().numpy().astype(np.float64)
     assert -(x @ (inst.to_scipy() @ x)) == pytest.approx(opt, abs=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["paper_q", "fixed_q", "storage_optimal", "box_reorth"])
+def test_graph_replays_match_eager_launches(case, precision, cfg1):
+    """On a non-null stream every iteration is a replay of a captured graph (one
+    per Lanczos step count, the iteration counter read on the device).  With
+    eager host work and synchronisations between the calls, every replayed
+    iteration's record, and the state after each call, equal the eager run's
+    bit for bit."""
+    need_gpu()
+    import torch
+    kw = dict(R=10, T=40, seed=SEED1, precision=precision)
+    if case == "fixed_q":
+        kw.update(q_mode=1, q_fixed=12)
+    elif case == "storage_optimal":
+        kw.update(basis_mode=1, omega_mode=1)
+    elif case == "box_reorth":
+        kw.update(constraint_set=1, reorth=1)
+    eager = make_solver(cfg1, **kw)
+    if case == "box_reorth":
+        eager.set_constraints(lo=np.full(cfg1.n, 0.9), hi=np.full(cfg1.n, 1.1))
+    eager.run()
+    stream = torch.cuda.Stream()
+    from paper_1912_02949_amd import Params, SketchyCGAL
+    g = SketchyCGAL(cfg1.row_ptr, cfg1.col, cfg1.val, cfg1.b, Params(**kw), stream=stream)
+    if case == "box_reorth":
+        g.set_constraints(lo=np.full(cfg1.n, 0.9), hi=np.full(cfg1.n, 1.1))
+    announce(f"graph replays {case} {precision}")
+    for chunk in (7, 13, 20):
+        g.step(chunk)
+        st = g.get_state()                     # synchronises; eager copies between the replays
+        assert st["t"] == 1 + sum((7, 13, 20)[:(7, 13, 20).index(chunk) + 1])
+    le, lg = eager.log(), g.log()
+    for key in le:
+        assert np.array_equal(le[key], lg[key], equal_nan=True), key
+    se, sg = eager.get_state(), g.get_state()
+    for key in ("z", "y", "S"):
+        assert torch.equal(se[key], sg[key]), key
+    assert se["p"] == sg["p"] and se["tau"] == sg["tau"]
