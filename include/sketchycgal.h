@@ -386,6 +386,135 @@ scg_status sketchycgal_batch_round(scg_batch* ctx, int32_t inst, const double* U
                                    double* weights, int32_t* best);
 void sketchycgal_batch_destroy(scg_batch* ctx);
 
+/* ======================================================================
+ * Phase retrieval (Section 7.3, eqn numerics-phase-retrieval-sdp): minimise
+ * tr X over complex Hermitian psd X subject to A X = b and tr X <= alpha,
+ * with coded diffraction measurements (Appendix F.1):
+ *     (A X)_{j,l} = a_{j,l}^* X a_{j,l},  a_{j,l}^* x = (DFT_n (conj(psi_j) x))_l,
+ * DFT_n unnormalised (entry (l, m) = exp(-2 pi i l m / n)), j < L waveforms.
+ * The solver is alg:sketchy-cgal over the trace-bounded set of Appendix D.2
+ * (H = alpha v v^* when the Ritz value xi < 0, else H = 0) in complex FP64:
+ * randomized Lanczos (alg:rand-lanczos) on the Hermitian D_t = C + A^*(w),
+ * the Nystrom sketch (alg:nystrom-sketch-supp) with a complex test matrix,
+ * and the rounding of Section 7.3.2 (chi = sqrt(lambda_1) u_1) with the
+ * relative error of Section 7.3.3.
+ *
+ * Scaling (eqn problem-scaling): C = I becomes I / sqrt(n); the A_i of
+ * waveform j are divided by ||psi_j||^2 (equal ||A_i||_F) and all by the
+ * norm N of the result, N^2 = n lambda_max(Q Q^T), Q_{j,m} =
+ * |psi_j(m)|^2 / ||psi_j||^2 (the Gram matrix of the A_i is block-circulant
+ * in l and its zero-frequency block holds the top eigenvalue), so ||A|| = 1;
+ * b is scaled the same way and by 1/alpha, alpha <- 1.
+ *
+ * Complex arrays are interleaved (re, im) doubles.  Measurement-indexed
+ * arrays (b, z, y, w, measure output) are L x n, entry j * n + l.  Random
+ * draws: the Lanczos start vector of iteration t and column c of Omega are
+ * complex with independent standard normal parts, complex element m being
+ * the Box-Muller pair (2m, 2m+1) of the Philox stream (seed; t, instance,
+ * purpose 2) and (seed; c, instance, purpose 3).
+ *
+ * Supported n: n = n1 n2 with n1, n2 <= 4096 and both products of 2, 3, 5
+ * (every n = 10^k, 2 <= k <= 7, qualifies); L <= 32; R <= 16.
+ * ====================================================================== */
+typedef struct {
+    int32_t  R;             /* sketch size, 1 <= R <= min(n, 16)                        */
+    int32_t  T;             /* iteration budget, >= 1                                     */
+    double   beta0;         /* beta0 > 0                                                  */
+    double   K;             /* dual bound K >= 0; +INF disables the guard                */
+    double   alpha;         /* trace bound alpha > 0; 0 selects 3 n (Section 7.3.3)       */
+    uint64_t seed;          /* Philox key                                                 */
+    int32_t  q_mode;        /* 0: q_t = ceil(t^(1/4) ln n); 1: q_t = q_fixed             */
+    int32_t  q_fixed;
+    int32_t  scale;         /* 1: the scaling above; 0: solve as given                    */
+    int32_t  trace_correct; /* 1: reconstruct corrects the trace to tau = tr X_T          */
+    int32_t  instance;      /* Philox counter word                                        */
+    int32_t  mask_groups;   /* inverse column pass: waveforms summed per workgroup group;
+                               0 = chosen from the tile count, else 1 .. L groups          */
+    int32_t  tile_cols;     /* columns per column-pass tile: 0 = chosen, else a power of
+                               two with n1 * tile_cols <= 4096                             */
+} scg_pr_params;
+
+/* Summary in ORIGINAL units: objective tr X, infeasibility ||A X - b||. */
+typedef struct {
+    int32_t t_done;
+    int32_t status_flags;     /* bit0: NaN/Inf seen                                       */
+    double objective;
+    double infeasibility;
+    double p_scaled, tau_scaled, alpha, alpha_scaled, c_F;
+    double op_norm;           /* N of the scaling (1 when unscaled)                       */
+    int32_t n1, n2;           /* the four-step split n = n1 n2                            */
+    int32_t tile_cols, row_tile, mask_groups;   /* launch shape of the DFT passes         */
+} scg_pr_info;
+
+typedef struct scg_pr_ctx scg_pr_ctx;
+
+/* Defaults: R = 5, T = 100, beta0 = 1, K = +inf, alpha = 3n, q_t schedule,
+ * scaling and trace correction on. */
+void scg_pr_default_params(scg_pr_params* p);
+
+/* Device workspace bytes for an n-dimensional signal and L waveforms;
+ * SCG_EINVAL for unsupported n or parameters. */
+scg_status scg_pr_workspace_size(const scg_pr_params* p, int64_t n, int32_t L, size_t* bytes);
+
+/* Create a context: copy psi, compute the scaling, scale b into the solver's
+ * order, draw (or copy) Omega, zero z, y, S, p, tau.
+ *   psi       device complex[L*n] waveforms (row j = psi_j)
+ *   b         device double[L*n] measurements, original units
+ *   omega     device complex[R*n] test matrix (column c contiguous) or NULL
+ *             to draw it from the Philox stream
+ *   workspace device, >= scg_pr_workspace_size bytes, 256-byte aligned, owned
+ *             by the caller until scg_pr_destroy
+ * Inputs are copied.  Synchronises.  SCG_EINVAL (sizes, parameters, a zero
+ * waveform), SCG_ENOMEM (short workspace), SCG_EHIP. */
+scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int32_t L, const double* psi,
+                       const double* b, const double* omega, void* workspace, size_t bytes, void* stream);
+
+/* Enqueue `iters` iterations (asynchronous).  SCG_ESTATE past T. */
+scg_status scg_pr_step(scg_pr_ctx* ctx, int32_t iters);
+
+/* y = (C + A^*(w)) x in scaled units: w device double[L*n] (dual weights,
+ * scaled units), x and y device complex[n].  Overwrites the iteration's
+ * dual weights (recomputed at the next step).  Synchronises. */
+scg_status scg_pr_apply(scg_pr_ctx* ctx, const double* w, const double* x, double* y);
+
+/* m = A(x x^*) in scaled units (s_j |DFT_n(conj(psi_j) x)_l|^2): x device
+ * complex[n], m device double[L*n].  Synchronises. */
+scg_status scg_pr_measure(scg_pr_ctx* ctx, const double* x, double* m);
+
+/* Iteration records (scg_iter_log; stop_obj, stop_feas, resid are NaN). */
+scg_status scg_pr_log(scg_pr_ctx* ctx, scg_iter_log* host_out, int32_t max, int32_t* count);
+
+/* Summary; with check_numeric, SCG_ENUMERIC once a NaN/Inf was seen. */
+scg_status scg_pr_summary(scg_pr_ctx* ctx, scg_pr_info* host_out, int32_t check_numeric);
+
+/* Checkpoint state in scaled units: z, y device double[L*n]; S device
+ * complex[R*n] (column c contiguous); any output may be NULL.  set_state
+ * puts the context before iteration t_next (1 <= t_next <= T+1).  Both
+ * synchronise. */
+scg_status scg_pr_get_state(scg_pr_ctx* ctx, int32_t* t_next, double* z, double* y, double* S, double* p,
+                            double* tau);
+scg_status scg_pr_set_state(scg_pr_ctx* ctx, int32_t t_next, const double* z, const double* y,
+                            const double* S, double p, double tau);
+
+/* NystromSketch.Reconstruct of the current sketch, FP64, scaled units:
+ * X_hat = U diag(lambda) U^*, U device complex[R*n] (column c contiguous,
+ * orthonormal), lambda device double[R] nonincreasing (trace-corrected to tau
+ * when enabled), err device double[R] or NULL (eqn sketch-err-supp).
+ * sigma = sqrt(n) eps(||S||_2); B = Omega^* S_sigma made Hermitian; on a
+ * Cholesky failure sigma grows tenfold, at most three times, then
+ * SCG_ENUMERIC.  The R x R steps run on the host.  Synchronises. */
+scg_status scg_pr_reconstruct(scg_pr_ctx* ctx, double* U, double* lambda, double* err);
+
+/* Rounding (Section 7.3.2): chi = sqrt(alpha lambda_j) u_j (original units)
+ * for the largest lambda_j (lowest index on ties).  U, lambda as written by
+ * scg_pr_reconstruct; chi device complex[n] or NULL; with chi_true (device
+ * complex[n]) rel_err (host) receives min_phi ||e^{i phi} chi - chi_true|| /
+ * ||chi_true|| (Section 7.3.3).  Synchronises. */
+scg_status scg_pr_round(scg_pr_ctx* ctx, const double* U, const double* lambda, const double* chi_true,
+                        double* chi, double* rel_err);
+
+scg_status scg_pr_destroy(scg_pr_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

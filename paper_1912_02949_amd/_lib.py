@@ -42,6 +42,25 @@ class scg_summary(C.Structure):
     ]
 
 
+class scg_pr_params(C.Structure):
+    _fields_ = [
+        ("R", C.c_int32), ("T", C.c_int32), ("beta0", C.c_double), ("K", C.c_double),
+        ("alpha", C.c_double), ("seed", C.c_uint64), ("q_mode", C.c_int32), ("q_fixed", C.c_int32),
+        ("scale", C.c_int32), ("trace_correct", C.c_int32), ("instance", C.c_int32),
+        ("mask_groups", C.c_int32), ("tile_cols", C.c_int32),
+    ]
+
+
+class scg_pr_info(C.Structure):
+    _fields_ = [
+        ("t_done", C.c_int32), ("status_flags", C.c_int32), ("objective", C.c_double),
+        ("infeasibility", C.c_double), ("p_scaled", C.c_double), ("tau_scaled", C.c_double),
+        ("alpha", C.c_double), ("alpha_scaled", C.c_double), ("c_F", C.c_double), ("op_norm", C.c_double),
+        ("n1", C.c_int32), ("n2", C.c_int32), ("tile_cols", C.c_int32), ("row_tile", C.c_int32),
+        ("mask_groups", C.c_int32),
+    ]
+
+
 EXPORTS = [
     "scg_default_params", "scg_workspace_size", "sketchycgal_init", "sketchycgal_step",
     "sketchycgal_reconstruct", "sketchycgal_log", "sketchycgal_summary", "sketchycgal_get_state",
@@ -52,6 +71,9 @@ EXPORTS = [
     "sketchycgal_batch_summary", "sketchycgal_batch_get_state", "sketchycgal_batch_set_state", "sketchycgal_batch_reconstruct",
     "sketchycgal_batch_destroy", "sketchycgal_batch_round", "sketchycgal_batch_set_beta0",
     "scg_round_csr",
+    "scg_pr_default_params", "scg_pr_workspace_size", "scg_pr_init", "scg_pr_step", "scg_pr_apply",
+    "scg_pr_measure", "scg_pr_log", "scg_pr_summary", "scg_pr_get_state", "scg_pr_set_state",
+    "scg_pr_reconstruct", "scg_pr_round", "scg_pr_destroy",
 ]
 
 _lib = None
@@ -99,10 +121,24 @@ def load() -> C.CDLL:
     lib.scg_round_csr.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, P(C.c_double), P(i32), vp]
     lib.sketchycgal_batch_destroy.argtypes = [vp]
     lib.sketchycgal_batch_destroy.restype = None
+    lib.scg_pr_default_params.argtypes = [P(scg_pr_params)]
+    lib.scg_pr_default_params.restype = None
+    lib.scg_pr_workspace_size.argtypes = [P(scg_pr_params), i64, i32, P(sz)]
+    lib.scg_pr_init.argtypes = [P(vp), P(scg_pr_params), i64, i32, vp, vp, vp, vp, sz, vp]
+    lib.scg_pr_step.argtypes = [vp, i32]
+    lib.scg_pr_apply.argtypes = [vp, vp, vp, vp]
+    lib.scg_pr_measure.argtypes = [vp, vp, vp]
+    lib.scg_pr_log.argtypes = [vp, P(scg_iter_log), i32, P(i32)]
+    lib.scg_pr_summary.argtypes = [vp, P(scg_pr_info), i32]
+    lib.scg_pr_get_state.argtypes = [vp, P(i32), vp, vp, vp, P(C.c_double), P(C.c_double)]
+    lib.scg_pr_set_state.argtypes = [vp, i32, vp, vp, vp, C.c_double, C.c_double]
+    lib.scg_pr_reconstruct.argtypes = [vp, vp, vp, vp]
+    lib.scg_pr_round.argtypes = [vp, vp, vp, vp, vp, P(C.c_double)]
+    lib.scg_pr_destroy.argtypes = [vp]
     lib.scg_status_string.argtypes = [C.c_int]
     lib.scg_status_string.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("scg_default_params", "sketchycgal_destroy", "scg_status_string"):
+        if name not in ("scg_default_params", "sketchycgal_destroy", "scg_status_string", "scg_pr_default_params"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -335,3 +335,157 @@ class BatchedSketchyCGAL:
         check(self.lib.sketchycgal_batch_reconstruct(self.ctx, inst, _ptr(U), _ptr(lam), _ptr(err)),
               "sketchycgal_batch_reconstruct")
         return U.view(R, n).t(), lam, err
+
+
+@dataclasses.dataclass
+class PhaseParams:
+    """Mirror of scg_pr_params (phase retrieval; defaults R = 5, alpha = 3 n)."""
+    R: int = 5
+    T: int = 100
+    beta0: float = 1.0
+    K: float = math.inf
+    alpha: float = 0.0            # 0: 3 n
+    seed: int = 0
+    q_mode: int = 0
+    q_fixed: int = 0
+    scale: int = 1
+    trace_correct: int = 1
+    instance: int = 0
+    mask_groups: int = 0          # inverse column pass: waveform groups (0: chosen)
+    tile_cols: int = 0            # column-pass tile width (0: chosen)
+
+    def to_c(self) -> _lib.scg_pr_params:
+        p = _lib.scg_pr_params()
+        for name, _ in _lib.scg_pr_params._fields_:
+            setattr(p, name, getattr(self, name))
+        return p
+
+
+def _cplx(x, device):
+    """Complex data as an interleaved float64 device tensor."""
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=torch.complex128).contiguous()
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(np.asarray(x, dtype=np.complex128))).to(device).contiguous()
+    return torch.view_as_real(t).contiguous()
+
+
+class PhaseRetrieval:
+    """Phase retrieval SDP on coded diffraction measurements (psi: L x n complex
+    waveforms, b: L x n measurements), solved by the library's complex engine."""
+
+    def __init__(self, psi, b, params: PhaseParams, omega=None, device="cuda:0", stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.params = params
+        ps = _cplx(psi, self.device)
+        self.L, self.n = int(ps.shape[0]), int(ps.shape[1])
+        bb = _dev(b, torch.float64, self.device).reshape(-1)
+        if bb.numel() != self.L * self.n:
+            raise ValueError("b must have L * n entries")
+        om = None
+        if omega is not None:   # n x R complex -> column-contiguous R x n
+            o = omega.t() if isinstance(omega, torch.Tensor) else np.asarray(omega).T
+            om = _cplx(o, self.device)
+            if om.shape[0] != params.R or om.shape[1] != self.n:
+                raise ValueError("omega must be n x R")
+        out = C.c_size_t()
+        cp = params.to_c()
+        check(self.lib.scg_pr_workspace_size(C.byref(cp), self.n, self.L, C.byref(out)), "scg_pr_workspace_size")
+        nbytes = out.value
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.scg_pr_init(C.byref(self.ctx), C.byref(cp), self.n, self.L, _ptr(ps), _ptr(bb), _ptr(om),
+                                   base + off, nbytes, self.stream.cuda_stream), "scg_pr_init")
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self.lib.scg_pr_destroy(ctx)
+            self.ctx = None
+
+    def step(self, iters: int = 1):
+        check(self.lib.scg_pr_step(self.ctx, iters), "scg_pr_step")
+
+    def run(self, iters: int | None = None):
+        self.step(self.params.T if iters is None else iters)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def apply(self, w, x) -> torch.Tensor:
+        """(C + A^*(w)) x in scaled units; w is L x n (scaled dual weights), x complex n."""
+        wt = _dev(w, torch.float64, self.device).reshape(-1)
+        xt = _cplx(x, self.device)
+        y = torch.empty(self.n, 2, dtype=torch.float64, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.scg_pr_apply(self.ctx, _ptr(wt), _ptr(xt), _ptr(y)), "scg_pr_apply")
+        return torch.view_as_complex(y)
+
+    def measure(self, x) -> torch.Tensor:
+        """A(x x^*) in scaled units, L x n."""
+        xt = _cplx(x, self.device)
+        m = torch.empty(self.L * self.n, dtype=torch.float64, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.scg_pr_measure(self.ctx, _ptr(xt), _ptr(m)), "scg_pr_measure")
+        return m.view(self.L, self.n)
+
+    def log(self) -> dict:
+        cap = self.params.T
+        arr = (_lib.scg_iter_log * cap)()
+        cnt = C.c_int32()
+        check(self.lib.scg_pr_log(self.ctx, arr, cap, C.byref(cnt)), "scg_pr_log")
+        return {name: np.array([getattr(arr[i], name) for i in range(cnt.value)])
+                for name, _ in _lib.scg_iter_log._fields_}
+
+    def summary(self, check_numeric: bool = True) -> dict:
+        s = _lib.scg_pr_info()
+        st = self.lib.scg_pr_summary(self.ctx, C.byref(s), 1 if check_numeric else 0)
+        check(st, "scg_pr_summary")
+        return {name: getattr(s, name) for name, _ in _lib.scg_pr_info._fields_}
+
+    def get_state(self) -> dict:
+        z = torch.empty(self.L * self.n, dtype=torch.float64, device=self.device)
+        y = torch.empty_like(z)
+        S = torch.empty(self.params.R, self.n, 2, dtype=torch.float64, device=self.device)
+        t = C.c_int32()
+        p = C.c_double()
+        tau = C.c_double()
+        check(self.lib.scg_pr_get_state(self.ctx, C.byref(t), _ptr(z), _ptr(y), _ptr(S), C.byref(p), C.byref(tau)),
+              "scg_pr_get_state")
+        return {"t": t.value, "z": z.view(self.L, self.n), "y": y.view(self.L, self.n),
+                "S": torch.view_as_complex(S).t(), "p": p.value, "tau": tau.value}
+
+    def set_state(self, t, z, y, S, p, tau):
+        """S: n x R complex (scaled units), z, y: L x n."""
+        zt = _dev(z, torch.float64, self.device).reshape(-1)
+        yt = _dev(y, torch.float64, self.device).reshape(-1)
+        St = _cplx(S.t() if isinstance(S, torch.Tensor) else np.asarray(S).T, self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.scg_pr_set_state(self.ctx, int(t), _ptr(zt), _ptr(yt), _ptr(St), float(p), float(tau)),
+              "scg_pr_set_state")
+
+    def reconstruct(self):
+        """(U n x R complex, lambda, err), scaled units."""
+        R = self.params.R
+        U = torch.empty(R, self.n, 2, dtype=torch.float64, device=self.device)
+        lam = torch.empty(R, dtype=torch.float64, device=self.device)
+        err = torch.empty(R, dtype=torch.float64, device=self.device)
+        check(self.lib.scg_pr_reconstruct(self.ctx, _ptr(U), _ptr(lam), _ptr(err)), "scg_pr_reconstruct")
+        return torch.view_as_complex(U).t(), lam, err
+
+    def round(self, U, lam, chi_true=None):
+        """chi = sqrt(alpha lambda_1) u_1 (original units) and, given chi_true, the relative error."""
+        Ut = _cplx(U.t() if isinstance(U, torch.Tensor) else np.asarray(U).T, self.device)
+        lt = _dev(lam, torch.float64, self.device)
+        ct = None if chi_true is None else _cplx(chi_true, self.device)
+        chi = torch.empty(self.n, 2, dtype=torch.float64, device=self.device)
+        rel = C.c_double(float("nan"))
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.scg_pr_round(self.ctx, _ptr(Ut), _ptr(lt), _ptr(ct), _ptr(chi),
+                                    C.byref(rel) if ct is not None else None), "scg_pr_round")
+        return torch.view_as_complex(chi), rel.value

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsketchycgal.so")
-SOURCES = ["scg_api.hip", "scg_reconstruct.hip", "scg_batched.hip", "scg_round.hip"]
+SOURCES = ["scg_api.hip", "scg_reconstruct.hip", "scg_batched.hip", "scg_round.hip", "scg_phase.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
