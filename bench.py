@@ -424,6 +424,51 @@ def solve_leg(torch, k: int, inst, precision: str, T: int, spmv_reps: int = 100,
     return out
 
 
+def phase_bytes(n: int, L: int, G: int) -> dict:
+    """Algorithmic bytes of the three passes of one phase retrieval product D v (complex FP64 = 16 B,
+    real FP64 = 8 B), each array counted once per pass: column pass v, psi, Y; row pass Y in, c, Y out;
+    inverse column pass Y, psi, v, the G group sums."""
+    return {"colfwd": 16 * n + 32 * L * n, "row": 40 * L * n, "colinv": 32 * L * n + 16 * n * (1 + G)}
+
+
+def phase_leg(torch, T: int) -> dict:
+    """Phase retrieval at the paper's largest size (n = 10^6, 12 coded diffraction patterns, R = 5,
+    alpha = 3n, FP64): T iterations timed as a whole, and the three passes of the D v product."""
+    import synth.phase as sp
+    from paper_1912_02949_amd.api import PhaseParams, PhaseRetrieval
+    n, L = 10 ** 6, 12
+    inst = sp.coded_diffraction(n, sp.PHASE_SEEDS[6], L=L)
+    prm = PhaseParams(R=5, T=T, seed=sp.PHASE_SEEDS[6])
+    s = PhaseRetrieval(inst.psi, inst.b, prm)
+    info = s.summary()
+    tm = s.time_apply(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run()
+    s.synchronize()
+    dt = time.perf_counter() - t0
+    lg = s.log()
+    qs = [int(q) for q in lg["q"]]
+    products = sum(q + 1 for q in qs)      # q Lanczos products and the measurement pass per iteration
+    byt = phase_bytes(n, L, info["mask_groups"])
+    passes = {}
+    for key in ("colfwd", "row", "colinv"):
+        gbs = byt[key] / (tm[key] * 1e-3) / 1e9
+        passes[key] = {"avg_us": tm[key] * 1e3, "algorithmic_bytes": byt[key], "achieved_GBps": gbs,
+                       "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    tot = sum(byt.values())
+    out = {"workload": "phase retrieval SDP, coded diffraction patterns, n = 10^6, L = 12 (d = 12n), R = 5, "
+                       "alpha = 3n, FP64 complex, first %d iterations" % T,
+           "n": n, "L": L, "split": [info["n1"], info["n2"]], "tile_cols": info["tile_cols"],
+           "mask_groups": info["mask_groups"], "iters_per_s": T / dt, "ms_per_iteration": 1e3 * dt / T,
+           "lanczos_steps": int(sum(qs)), "products_per_s": products / dt,
+           "product_us": tm["apply"] * 1e3, "passes": passes,
+           "product_algorithmic_GBps": tot / (tm["apply"] * 1e-3) / 1e9,
+           "infeasibility_rel": s.summary()["infeasibility"] / math.sqrt(float((inst.b * inst.b).sum()))}
+    del s
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +481,8 @@ def main():
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--batched-T", type=int, default=1000)
     ap.add_argument("--no-storage-optimal", action="store_true")
+    ap.add_argument("--phase-T", type=int, default=30, help="iterations of the phase retrieval leg (0: skip)")
+    ap.add_argument("--phase-only", action="store_true", help="only the phase retrieval leg")
     ap.add_argument("--probe-workload", type=int, default=2, choices=(2, 3, 5),
                     help="workload of --traffic-probe")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -485,6 +532,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"workload": kp, "shapes": shapes, "copy_bytes": 4 * a.numel(),
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
+        return
+
+    if args.phase_only:
+        print(json.dumps({"phase_retrieval": phase_leg(torch, args.phase_T)}), flush=True)
         return
 
     norm_b = math.sqrt(float((inst.b * inst.b).sum()))
@@ -570,6 +621,10 @@ def main():
             progress(f"workload {k}: {others[f'workload_{k}']['fp32']['iters_per_s']:.2f} CGAL iterations/s")
         w1 = workload1_leg(torch)
         progress("workload 1 done")
+    phase = None
+    if args.phase_T > 0:
+        phase = phase_leg(torch, args.phase_T)
+        progress(f"phase retrieval n=10^6: {phase['ms_per_iteration']:.1f} ms per iteration")
     cpu = None if args.no_cpu else cpu_baseline(inst, T, args.cpu_seconds)
 
     # the roofline object: the Lanczos SpMV of the largest workload (its working set far exceeds the
@@ -634,6 +689,7 @@ def main():
         "batched": batched,
         "other_workloads": others,
         "workload_1": w1,
+        "phase_retrieval": phase,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

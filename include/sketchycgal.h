@@ -432,6 +432,9 @@ typedef struct {
                                0 = chosen from the tile count, else 1 .. L groups          */
     int32_t  tile_cols;     /* columns per column-pass tile: 0 = chosen, else a power of
                                two with n1 * tile_cols <= 4096                             */
+    int32_t  mask_format;   /* 0: waveforms stored as one-byte codes into a dictionary when
+                               they take at most 256 distinct values (bitwise; the coded
+                               diffraction waveforms take 8), else whole; 1: always whole */
 } scg_pr_params;
 
 /* Summary in ORIGINAL units: objective tr X, infeasibility ||A X - b||. */
@@ -444,6 +447,7 @@ typedef struct {
     double op_norm;           /* N of the scaling (1 when unscaled)                       */
     int32_t n1, n2;           /* the four-step split n = n1 n2                            */
     int32_t tile_cols, row_tile, mask_groups;   /* launch shape of the DFT passes         */
+    int32_t mask_codes;       /* 1: waveforms stored as dictionary codes                  */
 } scg_pr_info;
 
 typedef struct scg_pr_ctx scg_pr_ctx;
@@ -512,6 +516,13 @@ scg_status scg_pr_reconstruct(scg_pr_ctx* ctx, double* U, double* lambda, double
  * ||chi_true|| (Section 7.3.3).  Synchronises. */
 scg_status scg_pr_round(scg_pr_ctx* ctx, const double* U, const double* lambda, const double* chi_true,
                         double* chi, double* rel_err);
+
+/* Average times (ms) of the three passes of one D v product, each launched
+ * `reps` times back to back on the context's stream (ms[0] column DFT pass,
+ * ms[1] fused row pass, ms[2] inverse column pass) and of the whole product
+ * (ms[3]), measured with HIP events; the operands are the dual weights and
+ * start vector of the next iteration.  Synchronises. */
+scg_status scg_pr_time_apply(scg_pr_ctx* ctx, int32_t reps, double* ms);
 
 scg_status scg_pr_destroy(scg_pr_ctx* ctx);
 

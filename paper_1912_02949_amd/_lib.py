@@ -47,7 +47,7 @@ class scg_pr_params(C.Structure):
         ("R", C.c_int32), ("T", C.c_int32), ("beta0", C.c_double), ("K", C.c_double),
         ("alpha", C.c_double), ("seed", C.c_uint64), ("q_mode", C.c_int32), ("q_fixed", C.c_int32),
         ("scale", C.c_int32), ("trace_correct", C.c_int32), ("instance", C.c_int32),
-        ("mask_groups", C.c_int32), ("tile_cols", C.c_int32),
+        ("mask_groups", C.c_int32), ("tile_cols", C.c_int32), ("mask_format", C.c_int32),
     ]
 
 
@@ -57,7 +57,7 @@ class scg_pr_info(C.Structure):
         ("infeasibility", C.c_double), ("p_scaled", C.c_double), ("tau_scaled", C.c_double),
         ("alpha", C.c_double), ("alpha_scaled", C.c_double), ("c_F", C.c_double), ("op_norm", C.c_double),
         ("n1", C.c_int32), ("n2", C.c_int32), ("tile_cols", C.c_int32), ("row_tile", C.c_int32),
-        ("mask_groups", C.c_int32),
+        ("mask_groups", C.c_int32), ("mask_codes", C.c_int32),
     ]
 
 
@@ -73,7 +73,7 @@ EXPORTS = [
     "scg_round_csr",
     "scg_pr_default_params", "scg_pr_workspace_size", "scg_pr_init", "scg_pr_step", "scg_pr_apply",
     "scg_pr_measure", "scg_pr_log", "scg_pr_summary", "scg_pr_get_state", "scg_pr_set_state",
-    "scg_pr_reconstruct", "scg_pr_round", "scg_pr_destroy",
+    "scg_pr_reconstruct", "scg_pr_round", "scg_pr_destroy", "scg_pr_time_apply",
 ]
 
 _lib = None
@@ -135,6 +135,7 @@ def load() -> C.CDLL:
     lib.scg_pr_reconstruct.argtypes = [vp, vp, vp, vp]
     lib.scg_pr_round.argtypes = [vp, vp, vp, vp, vp, P(C.c_double)]
     lib.scg_pr_destroy.argtypes = [vp]
+    lib.scg_pr_time_apply.argtypes = [vp, i32, P(C.c_double)]
     lib.scg_status_string.argtypes = [C.c_int]
     lib.scg_status_string.restype = C.c_char_p
     for name in EXPORTS:

@@ -353,6 +353,7 @@ class PhaseParams:
     instance: int = 0
     mask_groups: int = 0          # inverse column pass: waveform groups (0: chosen)
     tile_cols: int = 0            # column-pass tile width (0: chosen)
+    mask_format: int = 0          # 0: dictionary codes when the waveforms take <= 256 values; 1: whole
 
     def to_c(self) -> _lib.scg_pr_params:
         p = _lib.scg_pr_params()
@@ -477,6 +478,12 @@ class PhaseRetrieval:
         err = torch.empty(R, dtype=torch.float64, device=self.device)
         check(self.lib.scg_pr_reconstruct(self.ctx, _ptr(U), _ptr(lam), _ptr(err)), "scg_pr_reconstruct")
         return torch.view_as_complex(U).t(), lam, err
+
+    def time_apply(self, reps: int = 20) -> dict:
+        """Event-timed average ms of the three DFT passes of one product and of the whole product."""
+        ms = (C.c_double * 4)()
+        check(self.lib.scg_pr_time_apply(self.ctx, reps, ms), "scg_pr_time_apply")
+        return {"colfwd": ms[0], "row": ms[1], "colinv": ms[2], "apply": ms[3]}
 
     def round(self, U, lam, chi_true=None):
         """chi = sqrt(alpha lambda_1) u_1 (original units) and, given chi_true, the relative error."""

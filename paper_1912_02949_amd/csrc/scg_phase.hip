@@ -40,9 +40,9 @@ using namespace scg;
 
 namespace {
 
-constexpr int kFT = 256;              // threads of the DFT kernels
+constexpr int kFT = 512;              // threads of the DFT kernels (8 wave64)
 constexpr int kTile = 4096;           // complex values per LDS tile (64 KiB)
-constexpr int kEPT = kTile / kFT;     // tile values per thread
+constexpr int kFI = 256;              // threads of the inverse column pass (its sums stay in registers)
 constexpr int kMaxStages = 16;
 constexpr int kPQCap = 512;           // Lanczos steps per iteration at most
 constexpr int kPRMax = 16;            // sketch size at most
@@ -71,7 +71,10 @@ struct PrArgs {
     Fft f1, f2;
     const double2* twh;
     const double2* twl;
-    const double2* psi;       // L x n
+    const double2* psi;       // L x n (when the waveforms are stored whole)
+    const uint8_t* psic;      // L x n dictionary codes (when they take at most 256 values)
+    const double2* dict;      // the dictionary
+    int coded;
     const double* s;          // L
     const double* b;          // L x n, row-pass order
     double* z;
@@ -107,6 +110,25 @@ __device__ __forceinline__ double2 cscl(double2 a, double s) { return make_doubl
 template <bool INV>
 __device__ __forceinline__ double2 mi(double2 x) {
     return INV ? make_double2(-x.y, x.x) : make_double2(x.y, -x.x);
+}
+
+// psi_j(m): from the dictionary codes or the stored waveforms.
+__device__ __forceinline__ double2 psi_at(const PrArgs& A, size_t jm) {
+    return A.coded ? A.dict[A.psic[jm]] : A.psi[jm];
+}
+
+// Sum over an NT-thread workgroup (fixed order); red holds NT / 64 doubles.
+template <int NT = kFT>
+__device__ __forceinline__ double ft_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
 }
 
 // exp(-+2 pi i t / n) from the two-level table.
@@ -206,9 +228,9 @@ struct Radix<5, INV> {
 // k = j mod Ns (Ns the product of the earlier radices), transforms them and
 // stores them at (j / Ns) Ns R + k + r Ns.  All butterflies of a thread are
 // read before the barrier and written after it.
-template <int R, bool INV>
+template <int R, bool INV, int NT>
 __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, const double2* __restrict__ tw) {
-    constexpr int MB = (kEPT + R - 1) / R;
+    constexpr int MB = (kTile / NT + R - 1) / R;
     const int nseq = 1 << lns;
     const int nb = N / R;
     const int total = nb << lns;
@@ -217,7 +239,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, c
     int ob[MB];
 #pragma unroll
     for (int u = 0; u < MB; ++u) {
-        const int bb = threadIdx.x + u * kFT;
+        const int bb = threadIdx.x + u * NT;
         if (bb < total) {
             const int s = bb & (nseq - 1), j = bb >> lns;
             const int jq = j / Ns;
@@ -239,7 +261,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, c
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < MB; ++u) {
-        const int bb = threadIdx.x + u * kFT;
+        const int bb = threadIdx.x + u * NT;
         if (bb < total) {
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[ob[u] + ((r * Ns) << lns)] = v[u][r];
@@ -250,16 +272,16 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, c
 
 // In-place DFT (natural order in and out) of the nseq interleaved sequences.
 // The caller has made the tile visible to the workgroup (barrier).
-template <bool INV>
+template <bool INV, int NT>
 __device__ void fft_tile(double2* buf, const Fft& F, int lns) {
     int Ns = 1;
     for (int st = 0; st < F.ns; ++st) {
         const int R = F.rad[st];
-        if (R == 8) fft_pass<8, INV>(buf, F.N, lns, Ns, F.tw);
-        else if (R == 4) fft_pass<4, INV>(buf, F.N, lns, Ns, F.tw);
-        else if (R == 2) fft_pass<2, INV>(buf, F.N, lns, Ns, F.tw);
-        else if (R == 5) fft_pass<5, INV>(buf, F.N, lns, Ns, F.tw);
-        else fft_pass<3, INV>(buf, F.N, lns, Ns, F.tw);
+        if (R == 8) fft_pass<8, INV, NT>(buf, F.N, lns, Ns, F.tw);
+        else if (R == 4) fft_pass<4, INV, NT>(buf, F.N, lns, Ns, F.tw);
+        else if (R == 2) fft_pass<2, INV, NT>(buf, F.N, lns, Ns, F.tw);
+        else if (R == 5) fft_pass<5, INV, NT>(buf, F.N, lns, Ns, F.tw);
+        else fft_pass<3, INV, NT>(buf, F.N, lns, Ns, F.tw);
         Ns *= R;
     }
 }
@@ -274,7 +296,7 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
     const int m20 = blockIdx.x * A.tc;
     const double d = *dv;
     const int tot = A.n1 << A.ltc;
-    const double2* ps = A.psi + (size_t)j * A.n;
+    const size_t jn = (size_t)j * A.n;
     for (int idx = threadIdx.x; idx < tot; idx += kFT) {
         const int m1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
         double2 val = make_double2(0.0, 0.0);
@@ -283,12 +305,12 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
             double2 x = src[m];
             x.x /= d;
             x.y /= d;
-            val = cmulc(x, ps[m]);
+            val = cmulc(x, psi_at(A, jn + m));
         }
         buf[idx] = val;
     }
     __syncthreads();
-    fft_tile<false>(buf, A.f1, A.ltc);
+    fft_tile<false, kFT>(buf, A.f1, A.ltc);
     double2* Yj = A.Y + (size_t)j * A.n;
     for (int idx = threadIdx.x; idx < tot; idx += kFT) {
         const int k1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
@@ -303,7 +325,7 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
 template <int MODE>
 __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double eta, double* out) {
     __shared__ double2 buf[kTile];
-    __shared__ double red[kWaves];
+    __shared__ double red[kFT / 64];
     if (lanczos && A.sc->broken) return;
     const int j = blockIdx.y;
     const int k10 = blockIdx.x * A.rw;
@@ -314,7 +336,7 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
             buf[(e << A.lrw) + r] = (k1 < A.n1) ? Yj[(int64_t)k1 * A.n2 + e] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    fft_tile<false>(buf, A.f2, A.lrw);
+    fft_tile<false, kFT>(buf, A.f2, A.lrw);
     if (MODE == 0) {
         const double* cj = A.c + (size_t)j * A.n;
         for (int r = 0; r < A.rw; ++r) {
@@ -324,7 +346,7 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
                                                                                       cj[(int64_t)k1 * A.n2 + e]);
         }
         __syncthreads();
-        fft_tile<true>(buf, A.f2, A.lrw);
+        fft_tile<true, kFT>(buf, A.f2, A.lrw);
         for (int r = 0; r < A.rw; ++r) {
             const int k1 = k10 + r;
             if (k1 >= A.n1) continue;
@@ -356,9 +378,9 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
             }
         }
         const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-        a_r2 = block_sum(a_r2, red);
-        a_yzb = block_sum(a_yzb, red);
-        a_yy = block_sum(a_yy, red);
+        a_r2 = ft_sum(a_r2, red);
+        a_yzb = ft_sum(a_yzb, red);
+        a_yy = ft_sum(a_yy, red);
         if (threadIdx.x == 0) {
             A.p_meas[3 * wg + 0] = a_r2;
             A.p_meas[3 * wg + 1] = a_yzb;
@@ -379,37 +401,37 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
 
 // Inverse column pass summed over the waveforms of group g; group 0 adds the
 // C term x / sqrt(n) (x = src / *dv).  Writes P_g and the partial Re(x^* P_g).
-__global__ __launch_bounds__(kFT) void k_pr_colinv(PrArgs A, const double2* __restrict__ src, const double* dv,
+__global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __restrict__ src, const double* dv,
                                                   int lanczos) {
     __shared__ double2 buf[kTile];
-    __shared__ double red[kWaves];
+    __shared__ double red[kFI / 64];
     if (lanczos && A.sc->broken) return;
     const int g = blockIdx.y;
     const int m20 = blockIdx.x * A.tc;
     const int tot = A.n1 << A.ltc;
-    double2 acc[kEPT];
+    double2 acc[kTile / kFI];
 #pragma unroll
-    for (int u = 0; u < kEPT; ++u) acc[u] = make_double2(0.0, 0.0);
+    for (int u = 0; u < kTile / kFI; ++u) acc[u] = make_double2(0.0, 0.0);
     const int j0 = g * A.mpg, j1 = min(A.L, j0 + A.mpg);
     for (int j = j0; j < j1; ++j) {
         const double2* Zj = A.Y + (size_t)j * A.n;
-        const double2* ps = A.psi + (size_t)j * A.n;
+        const size_t jn = (size_t)j * A.n;
 #pragma unroll
-        for (int u = 0; u < kEPT; ++u) {
-            const int idx = threadIdx.x + u * kFT;
+        for (int u = 0; u < kTile / kFI; ++u) {
+            const int idx = threadIdx.x + u * kFI;
             if (idx < tot) {
                 const int k1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
                 buf[idx] = (m2 < A.n2) ? Zj[(int64_t)k1 * A.n2 + m2] : make_double2(0.0, 0.0);
             }
         }
         __syncthreads();
-        fft_tile<true>(buf, A.f1, A.ltc);
+        fft_tile<true, kFI>(buf, A.f1, A.ltc);
 #pragma unroll
-        for (int u = 0; u < kEPT; ++u) {
-            const int idx = threadIdx.x + u * kFT;
+        for (int u = 0; u < kTile / kFI; ++u) {
+            const int idx = threadIdx.x + u * kFI;
             if (idx < tot) {
                 const int m1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
-                if (m2 < A.n2) acc[u] = cadd(acc[u], cmul(ps[(int64_t)m1 * A.n2 + m2], buf[idx]));
+                if (m2 < A.n2) acc[u] = cadd(acc[u], cmul(psi_at(A, jn + (int64_t)m1 * A.n2 + m2), buf[idx]));
             }
         }
         __syncthreads();
@@ -418,8 +440,8 @@ __global__ __launch_bounds__(kFT) void k_pr_colinv(PrArgs A, const double2* __re
     double dot = 0.0;
     double2* Pg = A.P + (size_t)g * A.n;
 #pragma unroll
-    for (int u = 0; u < kEPT; ++u) {
-        const int idx = threadIdx.x + u * kFT;
+    for (int u = 0; u < kTile / kFI; ++u) {
+        const int idx = threadIdx.x + u * kFI;
         if (idx < tot) {
             const int m1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
             if (m2 < A.n2) {
@@ -434,7 +456,7 @@ __global__ __launch_bounds__(kFT) void k_pr_colinv(PrArgs A, const double2* __re
             }
         }
     }
-    dot = block_sum(dot, red);
+    dot = ft_sum<kFI>(dot, red);
     if (threadIdx.x == 0) A.p_col[(size_t)g * gridDim.x + blockIdx.x] = dot;
 }
 
@@ -976,8 +998,8 @@ struct scg_pr_ctx {
 namespace {
 
 struct Layout {
-    size_t psi, s, b, z, y, c, Y, P, V, xr, Om, S, Wk, small, tw1, tw2, twh, twl, p_col, p_upd, p_meas, p_prep,
-        p_sk, p_red, sc, log, total;
+    size_t psi, psic, dict, s, b, z, y, c, Y, P, V, xr, Om, S, Wk, small, tw1, tw2, twh, twl, p_col, p_upd, p_meas,
+        p_prep, p_sk, p_red, sc, log, total;
 };
 
 struct Shape {
@@ -1045,6 +1067,8 @@ Layout layout(const scg_pr_params* p, int64_t n, int L, const Shape& sh, int qca
     };
     const size_t cn = sizeof(double2) * (size_t)n, rn = sizeof(double) * (size_t)n;
     l.psi = take(cn * L);
+    l.psic = take((size_t)n * L);
+    l.dict = take(sizeof(double2) * 256);
     l.s = take(sizeof(double) * kPLMax);
     l.b = take(rn * L);
     l.z = take(rn * L);
@@ -1088,6 +1112,7 @@ bool params_ok(const scg_pr_params* p, int64_t n, int L) {
     if (p->trace_correct != 0 && p->trace_correct != 1) return false;
     if (p->mask_groups < 0 || p->mask_groups > L) return false;
     if (p->tile_cols < 0) return false;
+    if (p->mask_format != 0 && p->mask_format != 1) return false;
     if (L < 1 || L > kPLMax) return false;
     if (qmax_for(p, n) > kPQCap) return false;
     return true;
@@ -1127,7 +1152,7 @@ void enqueue_apply(scg_pr_ctx* c, const double2* src, const double* dv, int lanc
     PrArgs& A = c->A;
     hipLaunchKernelGGL(k_pr_colfwd, dim3(A.ntc, A.L), dim3(kFT), 0, c->stream, A, src, dv, lanczos);
     hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, c->stream, A, lanczos, 0.0, (double*)nullptr);
-    hipLaunchKernelGGL(k_pr_colinv, dim3(A.ntc, A.G), dim3(kFT), 0, c->stream, A, src, dv, lanczos);
+    hipLaunchKernelGGL(k_pr_colinv, dim3(A.ntc, A.G), dim3(kFI), 0, c->stream, A, src, dv, lanczos);
 }
 
 int q_of(const scg_pr_ctx* c, int t) {
@@ -1195,6 +1220,7 @@ void scg_pr_default_params(scg_pr_params* p) {
     p->instance = 0;
     p->mask_groups = 0;
     p->tile_cols = 0;
+    p->mask_format = 0;
 }
 
 scg_status scg_pr_workspace_size(const scg_pr_params* p, int64_t n, int32_t L, size_t* bytes) {
@@ -1219,6 +1245,7 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
     std::vector<int> r1, r2;
     if (!radix_plan(sh.n1, r1) || !radix_plan(sh.n2, r2)) return SCG_EINVAL;
 
+    const double2* psi_in = (const double2*)psi;
     scg_pr_ctx* c = new scg_pr_ctx();
     c->prm = *p;
     c->n = n;
@@ -1241,7 +1268,10 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
     A.mpg = sh.mpg;
     A.ntc = sh.ntc;
     A.nrw = sh.nrw;
-    A.psi = (const double2*)(w + l.psi);
+    A.psi = psi_in;   // the caller's copy until the waveforms are stored below
+    A.psic = (const uint8_t*)(w + l.psic);
+    A.dict = (const double2*)(w + l.dict);
+    A.coded = 0;
     A.s = (const double*)(w + l.s);
     A.b = (const double*)(w + l.b);
     A.z = (double*)(w + l.z);
@@ -1292,8 +1322,6 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
             hipStreamSynchronize(st))
             return fail(SCG_EHIP);
     }
-    if (hipMemcpyAsync((void*)A.psi, psi, sizeof(double2) * (size_t)n * L, hipMemcpyDeviceToDevice, st))
-        return fail(SCG_EHIP);
     // scaling (eqn problem-scaling): s_j = 1 / (||psi_j||^2 N), N = sqrt(n lambda_max(Q Q^T))
     const int gn = grid_for(n);
     std::vector<double> s0(L, 1.0), sv(L, 1.0);
@@ -1318,6 +1346,45 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
         const double lmax = max_singular(Q, L);   // symmetric psd: singular values = eigenvalues
         c->opnorm = std::sqrt((double)n * lmax);
         for (int j = 0; j < L; ++j) sv[j] = s0[j] / c->opnorm;
+    }
+    // store the waveforms: as one-byte codes into a dictionary when they take at most 256 values
+    // (compared bitwise), else whole
+    {
+        bool coded = false;
+        if (p->mask_format == 0) {
+            std::vector<double2> h((size_t)n * L);
+            if (hipMemcpyAsync(h.data(), psi, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, st) ||
+                hipStreamSynchronize(st))
+                return fail(SCG_EHIP);
+            std::vector<double2> dict;
+            std::vector<uint8_t> codes(h.size());
+            coded = true;
+            for (size_t i = 0; i < h.size() && coded; ++i) {
+                int k = 0;
+                const int nd = (int)dict.size();
+                for (; k < nd; ++k)
+                    if (std::memcmp(&dict[k], &h[i], sizeof(double2)) == 0) break;
+                if (k == nd) {
+                    if (nd == 256) {
+                        coded = false;
+                        break;
+                    }
+                    dict.push_back(h[i]);
+                }
+                codes[i] = (uint8_t)k;
+            }
+            if (coded) {
+                if (hipMemcpyAsync((void*)A.psic, codes.data(), codes.size(), hipMemcpyHostToDevice, st) ||
+                    hipMemcpyAsync((void*)A.dict, dict.data(), sizeof(double2) * dict.size(), hipMemcpyHostToDevice,
+                                   st) ||
+                    hipStreamSynchronize(st))
+                    return fail(SCG_EHIP);
+            }
+        }
+        A.psi = (const double2*)(w + l.psi);
+        A.coded = coded ? 1 : 0;
+        if (!coded && hipMemcpyAsync((void*)A.psi, psi, sizeof(double2) * (size_t)n * L, hipMemcpyDeviceToDevice, st))
+            return fail(SCG_EHIP);
     }
     c->s = sv;
     if (hipMemcpyAsync((void*)A.s, sv.data(), sizeof(double) * L, hipMemcpyHostToDevice, st)) return fail(SCG_EHIP);
@@ -1419,6 +1486,7 @@ scg_status scg_pr_summary(scg_pr_ctx* c, scg_pr_info* o, int32_t check_numeric) 
     o->tile_cols = c->A.tc;
     o->row_tile = c->A.rw;
     o->mask_groups = c->A.G;
+    o->mask_codes = c->A.coded;
     if (check_numeric && (hs.flags & 1)) return SCG_ENUMERIC;
     return SCG_OK;
 }
@@ -1592,6 +1660,45 @@ scg_status scg_pr_round(scg_pr_ctx* c, const double* U, const double* lambda, co
         *rel_err = std::sqrt(std::max(0.0, r[0] + r[3] - 2.0 * m)) / std::sqrt(r[3]);
     }
     return SCG_OK;
+}
+
+scg_status scg_pr_time_apply(scg_pr_ctx* c, int32_t reps, double* ms) {
+    if (!c || reps < 1 || !ms) return SCG_EINVAL;
+    PrArgs& A = c->A;
+    hipStream_t st = c->stream;
+    const int t = std::min(c->t_next, c->prm.T);
+    // valid operands: the dual weights of iteration t and its start vector in V[0]
+    hipLaunchKernelGGL(k_pr_prep, dim3(grid_for((int64_t)A.L * A.n)), dim3(kBlock), 0, st, A,
+                       c->prm.beta0 * std::sqrt(t + 1.0));
+    const int gh = grid_for((A.n + 1) / 2);
+    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, (uint64_t)t,
+                       (uint64_t)c->prm.instance, 1);
+    hipLaunchKernelGGL(k_pr_norm, dim3(1), dim3(kBlock), 0, st, A, 0, gh, 0);
+    const double2* v = A.V;
+    const double* dv = &A.sc->nrm[0];
+    hipEvent_t ev[5];
+    for (auto& e : ev) PR_HIP(hipEventCreate(&e));
+    enqueue_apply(c, v, dv, 0);   // warm-up
+    PR_HIP(hipEventRecord(ev[0], st));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(k_pr_colfwd, dim3(A.ntc, A.L), dim3(kFT), 0, st, A, v, dv, 0);
+    PR_HIP(hipEventRecord(ev[1], st));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, st, A, 0, 0.0, (double*)nullptr);
+    PR_HIP(hipEventRecord(ev[2], st));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(k_pr_colinv, dim3(A.ntc, A.G), dim3(kFI), 0, st, A, v, dv, 0);
+    PR_HIP(hipEventRecord(ev[3], st));
+    for (int r = 0; r < reps; ++r) enqueue_apply(c, v, dv, 0);
+    PR_HIP(hipEventRecord(ev[4], st));
+    PR_HIP(hipEventSynchronize(ev[4]));
+    for (int i = 0; i < 4; ++i) {
+        float f = 0.f;
+        PR_HIP(hipEventElapsedTime(&f, ev[i], ev[i + 1]));
+        ms[i] = (double)f / reps;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return hipGetLastError() == hipSuccess ? SCG_OK : SCG_EHIP;
 }
 
 }  // extern "C"

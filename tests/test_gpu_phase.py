@@ -57,6 +57,7 @@ SHAPES = [
     (10000, 12, {"tile_cols": 8, "mask_groups": 1}),
     (2 * 3 ** 4 * 5 ** 3 * 2, 3, {}),           # 40500 = 10 x 4050: radix 3 and 5 in both passes
     (100000, 12, {}),                           # n1 = 25, n2 = 4000
+    (10000, 12, {"mask_format": 1}),            # waveforms stored whole
 ]
 
 
@@ -70,6 +71,7 @@ def test_apply_and_measure_match_oracle(n, L, shape):
     announce(f"split {info['n1']} x {info['n2']} tiles {info['tile_cols']} rows {info['row_tile']} "
              f"groups {info['mask_groups']}")
     assert info["n1"] * info["n2"] == n
+    assert info["mask_codes"] == (0 if shape.get("mask_format") == 1 else 1)   # 8 distinct waveform values
     sc, bs, _, c_F = scale_phase(inst.psi, inst.b, 3.0 * n)
     assert abs(info["op_norm"] - operator_norm(inst.psi, 1.0 / np.sum(np.abs(inst.psi) ** 2, axis=1))) \
         < 1e-12 * info["op_norm"]
@@ -198,6 +200,22 @@ def test_full_size_first_iteration():
     assert maxrel(g["S"].cpu().numpy(), ref.S) < 1e-9
 
 
+def test_gaussian_waveforms_are_stored_whole():
+    """Waveforms with more than 256 distinct values cannot use the dictionary; the operator still matches."""
+    need_gpu()
+    n, L = 4800, 4
+    inst = coded_diffraction(n, 8, L=L, masks="gaussian")
+    s = make(inst, R=2, T=2)
+    assert s.summary()["mask_codes"] == 0
+    sc, _, _, c_F = scale_phase(inst.psi, inst.b, 3.0 * n)
+    op = CDPOperator(inst.psi, sc)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    w = rng.standard_normal((L, n))
+    assert maxrel(s.apply(w, x).cpu().numpy(), x / c_F + op.adjoint_apply(w, x)) < 1e-12
+    assert maxrel(s.measure(x).cpu().numpy(), op.forward(x)) < 1e-12
+
+
 def test_validation_errors_and_nonfinite_flag():
     need_gpu()
     from paper_1912_02949_amd._lib import SCGError, SCG_EINVAL, SCG_ENUMERIC, SCG_ESTATE
@@ -206,7 +224,8 @@ def test_validation_errors_and_nonfinite_flag():
         make(inst, R=2, T=2)
     assert e.value.status == SCG_EINVAL
     inst = coded_diffraction(64, 1, L=3)
-    for bad in (dict(R=17), dict(R=0), dict(T=0), dict(beta0=-1.0), dict(tile_cols=3), dict(mask_groups=4)):
+    for bad in (dict(R=17), dict(R=0), dict(T=0), dict(beta0=-1.0), dict(tile_cols=3), dict(mask_groups=4),
+                dict(mask_format=2)):
         with pytest.raises(SCGError) as e:
             make(inst, **{**dict(R=2, T=2), **bad})
         assert e.value.status == SCG_EINVAL, bad
