@@ -424,11 +424,31 @@ def solve_leg(torch, k: int, inst, precision: str, T: int, spmv_reps: int = 100,
     return out
 
 
-def phase_bytes(n: int, L: int, G: int) -> dict:
+def phase_bytes(n: int, L: int, G: int, psi_bytes: int) -> dict:
     """Algorithmic bytes of the three passes of one phase retrieval product D v (complex FP64 = 16 B,
-    real FP64 = 8 B), each array counted once per pass: column pass v, psi, Y; row pass Y in, c, Y out;
-    inverse column pass Y, psi, v, the G group sums."""
-    return {"colfwd": 16 * n + 32 * L * n, "row": 40 * L * n, "colinv": 32 * L * n + 16 * n * (1 + G)}
+    real FP64 = 8 B, a waveform entry psi_bytes: 1 as a dictionary code, 16 whole), each array counted
+    once per pass: column pass v, psi, Y; row pass Y in, c, Y out; inverse column pass Y, psi, v, the G
+    group sums."""
+    return {"colfwd": 16 * n + (16 + psi_bytes) * L * n, "row": 40 * L * n,
+            "colinv": (16 + psi_bytes) * L * n + 16 * n * (1 + G)}
+
+
+def phase_sweep(torch) -> list:
+    """Per-pass times of the n = 10^6 product for several column-tile widths and waveform groups."""
+    import synth.phase as sp
+    from paper_1912_02949_amd.api import PhaseParams, PhaseRetrieval
+    n, L = 10 ** 6, 12
+    inst = sp.coded_diffraction(n, sp.PHASE_SEEDS[6], L=L)
+    rows = []
+    for tc, G in ((16, 4), (16, 1), (16, 2), (16, 3), (16, 6), (16, 12), (8, 4), (4, 4)):
+        s = PhaseRetrieval(inst.psi, inst.b, PhaseParams(R=5, T=2, seed=1, tile_cols=tc, mask_groups=G))
+        tm = s.time_apply(20)
+        info = s.summary()
+        rows.append({"tile_cols": info["tile_cols"], "mask_groups": info["mask_groups"],
+                     **{k: round(v * 1e3, 1) for k, v in tm.items()}})
+        progress(f"phase sweep {rows[-1]}")
+        del s
+    return rows
 
 
 def phase_leg(torch, T: int) -> dict:
@@ -450,7 +470,7 @@ def phase_leg(torch, T: int) -> dict:
     lg = s.log()
     qs = [int(q) for q in lg["q"]]
     products = sum(q + 1 for q in qs)      # q Lanczos products and the measurement pass per iteration
-    byt = phase_bytes(n, L, info["mask_groups"])
+    byt = phase_bytes(n, L, info["mask_groups"], 1 if info["mask_codes"] else 16)
     passes = {}
     for key in ("colfwd", "row", "colinv"):
         gbs = byt[key] / (tm[key] * 1e-3) / 1e9
@@ -460,7 +480,7 @@ def phase_leg(torch, T: int) -> dict:
     out = {"workload": "phase retrieval SDP, coded diffraction patterns, n = 10^6, L = 12 (d = 12n), R = 5, "
                        "alpha = 3n, FP64 complex, first %d iterations" % T,
            "n": n, "L": L, "split": [info["n1"], info["n2"]], "tile_cols": info["tile_cols"],
-           "mask_groups": info["mask_groups"], "iters_per_s": T / dt, "ms_per_iteration": 1e3 * dt / T,
+           "mask_groups": info["mask_groups"], "waveform_codes": bool(info["mask_codes"]), "iters_per_s": T / dt, "ms_per_iteration": 1e3 * dt / T,
            "lanczos_steps": int(sum(qs)), "products_per_s": products / dt,
            "product_us": tm["apply"] * 1e3, "passes": passes,
            "product_algorithmic_GBps": tot / (tm["apply"] * 1e-3) / 1e9,
@@ -483,6 +503,8 @@ def main():
     ap.add_argument("--no-storage-optimal", action="store_true")
     ap.add_argument("--phase-T", type=int, default=30, help="iterations of the phase retrieval leg (0: skip)")
     ap.add_argument("--phase-only", action="store_true", help="only the phase retrieval leg")
+    ap.add_argument("--phase-sweep", action="store_true",
+                    help="only per-pass times of the phase retrieval product over tile widths and waveform groups")
     ap.add_argument("--probe-workload", type=int, default=2, choices=(2, 3, 5),
                     help="workload of --traffic-probe")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -534,6 +556,9 @@ def main():
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
         return
 
+    if args.phase_sweep:
+        print(json.dumps({"phase_sweep": phase_sweep(torch)}), flush=True)
+        return
     if args.phase_only:
         print(json.dumps({"phase_retrieval": phase_leg(torch, args.phase_T)}), flush=True)
         return

@@ -428,8 +428,9 @@ typedef struct {
     int32_t  scale;         /* 1: the scaling above; 0: solve as given                    */
     int32_t  trace_correct; /* 1: reconstruct corrects the trace to tau = tr X_T          */
     int32_t  instance;      /* Philox counter word                                        */
-    int32_t  mask_groups;   /* inverse column pass: waveforms summed per workgroup group;
-                               0 = chosen from the tile count, else 1 .. L groups          */
+    int32_t  mask_groups;   /* inverse column pass: the waveforms are split into this many
+                               groups, each summed by its own workgroups into its own
+                               partial product; 0 = one group, else 1 .. L                 */
     int32_t  tile_cols;     /* columns per column-pass tile: 0 = chosen, else a power of
                                two with n1 * tile_cols <= 4096                             */
     int32_t  mask_format;   /* 0: waveforms stored as one-byte codes into a dictionary when

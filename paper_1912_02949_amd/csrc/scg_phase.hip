@@ -42,7 +42,8 @@ namespace {
 
 constexpr int kFT = 512;              // threads of the DFT kernels (8 wave64)
 constexpr int kTile = 4096;           // complex values per LDS tile (64 KiB)
-constexpr int kFI = 256;              // threads of the inverse column pass (its sums stay in registers)
+constexpr int kTileP = kTile + kTile / 8;   // the tile with one padding value after every eight
+constexpr int kFI = 1024;             // threads of the inverse column pass (its sums stay in registers)
 constexpr int kMaxStages = 16;
 constexpr int kPQCap = 512;           // Lanczos steps per iteration at most
 constexpr int kPRMax = 16;            // sketch size at most
@@ -53,8 +54,16 @@ constexpr int kGU = 1024;             // workgroups of the streaming passes (at 
 struct Fft {
     int N, ns;
     int rad[kMaxStages];
-    const double2* tw;                // exp(-2 pi i t / N), t < N
+    const double2* tw;                // [0, 64): exp(-2 pi i 64 h / N); [64, 128): exp(-2 pi i l / N)
 };
+
+// The DFT passes read exp(-2 pi i t / N) as the product of two entries of a
+// 128-value table staged in LDS (high part t >> 6, low part t & 63).
+constexpr int kTwLds = 128;
+
+__device__ __forceinline__ void load_tw(double2* tws, const Fft& F, int nt) {
+    for (int i = threadIdx.x; i < kTwLds; i += nt) tws[i] = F.tw[i];
+}
 
 struct PrScalars {
     double omega[kPQCap];
@@ -111,6 +120,11 @@ template <bool INV>
 __device__ __forceinline__ double2 mi(double2 x) {
     return INV ? make_double2(-x.y, x.x) : make_double2(x.y, -x.x);
 }
+
+// LDS position of tile value i: one padding value after every eight, so that
+// the eight lanes a 16-byte LDS access serves per cycle fall into distinct
+// bank groups also when a pass stores its outputs R or Ns values apart.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
 
 // psi_j(m): from the dictionary codes or the stored waveforms.
 __device__ __forceinline__ double2 psi_at(const PrArgs& A, size_t jm) {
@@ -223,13 +237,13 @@ struct Radix<5, INV> {
 };
 
 // One Stockham pass of radix R over nseq = 2^lns interleaved sequences of
-// length N held at buf[e * nseq + s]: butterfly j of sequence s takes the R
+// length N held at buf[pad(e * nseq + s)]: butterfly j of sequence s takes the R
 // values at j + r N / R, multiplies them by exp(-+2 pi i k r / (Ns R)) with
 // k = j mod Ns (Ns the product of the earlier radices), transforms them and
 // stores them at (j / Ns) Ns R + k + r Ns.  All butterflies of a thread are
 // read before the barrier and written after it.
 template <int R, bool INV, int NT>
-__device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, const double2* __restrict__ tw) {
+__device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, const double2* tws) {
     constexpr int MB = (kTile / NT + R - 1) / R;
     const int nseq = 1 << lns;
     const int nb = N / R;
@@ -246,9 +260,10 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, c
             const int k = j - jq * Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                double2 x = buf[((j + r * nb) << lns) + s];
+                double2 x = buf[pad(((j + r * nb) << lns) + s)];
                 if (r > 0) {
-                    double2 w = tw[k * r * tstride];
+                    const int t = k * r * tstride;
+                    double2 w = cmul(tws[t >> 6], tws[64 + (t & 63)]);
                     if (INV) w.y = -w.y;
                     x = cmul(x, w);
                 }
@@ -264,7 +279,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, c
         const int bb = threadIdx.x + u * NT;
         if (bb < total) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[ob[u] + ((r * Ns) << lns)] = v[u][r];
+            for (int r = 0; r < R; ++r) buf[pad(ob[u] + ((r * Ns) << lns))] = v[u][r];
         }
     }
     __syncthreads();
@@ -273,15 +288,15 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, c
 // In-place DFT (natural order in and out) of the nseq interleaved sequences.
 // The caller has made the tile visible to the workgroup (barrier).
 template <bool INV, int NT>
-__device__ void fft_tile(double2* buf, const Fft& F, int lns) {
+__device__ void fft_tile(double2* buf, const Fft& F, int lns, const double2* tws) {
     int Ns = 1;
     for (int st = 0; st < F.ns; ++st) {
         const int R = F.rad[st];
-        if (R == 8) fft_pass<8, INV, NT>(buf, F.N, lns, Ns, F.tw);
-        else if (R == 4) fft_pass<4, INV, NT>(buf, F.N, lns, Ns, F.tw);
-        else if (R == 2) fft_pass<2, INV, NT>(buf, F.N, lns, Ns, F.tw);
-        else if (R == 5) fft_pass<5, INV, NT>(buf, F.N, lns, Ns, F.tw);
-        else fft_pass<3, INV, NT>(buf, F.N, lns, Ns, F.tw);
+        if (R == 8) fft_pass<8, INV, NT>(buf, F.N, lns, Ns, tws);
+        else if (R == 4) fft_pass<4, INV, NT>(buf, F.N, lns, Ns, tws);
+        else if (R == 2) fft_pass<2, INV, NT>(buf, F.N, lns, Ns, tws);
+        else if (R == 5) fft_pass<5, INV, NT>(buf, F.N, lns, Ns, tws);
+        else fft_pass<3, INV, NT>(buf, F.N, lns, Ns, tws);
         Ns *= R;
     }
 }
@@ -290,13 +305,15 @@ __device__ void fft_tile(double2* buf, const Fft& F, int lns) {
 // Column pass of DFT_n(conj(psi_j) x) for x = src / *dv, tile of tc columns.
 __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __restrict__ src, const double* dv,
                                                   int lanczos) {
-    __shared__ double2 buf[kTile];
+    __shared__ double2 buf[kTileP];
+    __shared__ double2 tws[kTwLds];
     if (lanczos && A.sc->broken) return;
     const int j = blockIdx.y;
     const int m20 = blockIdx.x * A.tc;
     const double d = *dv;
     const int tot = A.n1 << A.ltc;
     const size_t jn = (size_t)j * A.n;
+    load_tw(tws, A.f1, kFT);
     for (int idx = threadIdx.x; idx < tot; idx += kFT) {
         const int m1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
         double2 val = make_double2(0.0, 0.0);
@@ -307,14 +324,14 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
             x.y /= d;
             val = cmulc(x, psi_at(A, jn + m));
         }
-        buf[idx] = val;
+        buf[pad(idx)] = val;
     }
     __syncthreads();
-    fft_tile<false, kFT>(buf, A.f1, A.ltc);
+    fft_tile<false, kFT>(buf, A.f1, A.ltc, tws);
     double2* Yj = A.Y + (size_t)j * A.n;
     for (int idx = threadIdx.x; idx < tot; idx += kFT) {
         const int k1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
-        if (m2 < A.n2) Yj[(int64_t)k1 * A.n2 + m2] = cmul(buf[idx], twn(A, (int64_t)k1 * m2));
+        if (m2 < A.n2) Yj[(int64_t)k1 * A.n2 + m2] = cmul(buf[pad(idx)], twn(A, (int64_t)k1 * m2));
     }
 }
 
@@ -324,36 +341,38 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
 // ||z - b||^2, <y, z - b>, ||y||^2.  MODE 2: m written to out in natural order.
 template <int MODE>
 __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double eta, double* out) {
-    __shared__ double2 buf[kTile];
+    __shared__ double2 buf[kTileP];
+    __shared__ double2 tws[kTwLds];
     __shared__ double red[kFT / 64];
     if (lanczos && A.sc->broken) return;
     const int j = blockIdx.y;
     const int k10 = blockIdx.x * A.rw;
     double2* Yj = A.Y + (size_t)j * A.n;
+    load_tw(tws, A.f2, kFT);
     for (int r = 0; r < A.rw; ++r) {
         const int k1 = k10 + r;
         for (int e = threadIdx.x; e < A.n2; e += kFT)
-            buf[(e << A.lrw) + r] = (k1 < A.n1) ? Yj[(int64_t)k1 * A.n2 + e] : make_double2(0.0, 0.0);
+            buf[pad((e << A.lrw) + r)] = (k1 < A.n1) ? Yj[(int64_t)k1 * A.n2 + e] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    fft_tile<false, kFT>(buf, A.f2, A.lrw);
+    fft_tile<false, kFT>(buf, A.f2, A.lrw, tws);
     if (MODE == 0) {
         const double* cj = A.c + (size_t)j * A.n;
         for (int r = 0; r < A.rw; ++r) {
             const int k1 = k10 + r;
             if (k1 >= A.n1) continue;
-            for (int e = threadIdx.x; e < A.n2; e += kFT) buf[(e << A.lrw) + r] = cscl(buf[(e << A.lrw) + r],
+            for (int e = threadIdx.x; e < A.n2; e += kFT) buf[pad((e << A.lrw) + r)] = cscl(buf[pad((e << A.lrw) + r)],
                                                                                       cj[(int64_t)k1 * A.n2 + e]);
         }
         __syncthreads();
-        fft_tile<true, kFT>(buf, A.f2, A.lrw);
+        fft_tile<true, kFT>(buf, A.f2, A.lrw, tws);
         for (int r = 0; r < A.rw; ++r) {
             const int k1 = k10 + r;
             if (k1 >= A.n1) continue;
             for (int e = threadIdx.x; e < A.n2; e += kFT) {
                 double2 w = twn(A, (int64_t)k1 * e);
                 w.y = -w.y;
-                Yj[(int64_t)k1 * A.n2 + e] = cmul(buf[(e << A.lrw) + r], w);
+                Yj[(int64_t)k1 * A.n2 + e] = cmul(buf[pad((e << A.lrw) + r)], w);
             }
         }
     } else if (MODE == 1) {
@@ -365,7 +384,7 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
             const int k1 = k10 + r;
             if (k1 >= A.n1) continue;
             for (int e = threadIdx.x; e < A.n2; e += kFT) {
-                const double2 X = buf[(e << A.lrw) + r];
+                const double2 X = buf[pad((e << A.lrw) + r)];
                 const double m = sj * (X.x * X.x + X.y * X.y);
                 const size_t pos = (size_t)j * A.n + (size_t)k1 * A.n2 + e;
                 const double zn = keep * A.z[pos] + eh * m;
@@ -392,7 +411,7 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
             const int k1 = k10 + r;
             if (k1 >= A.n1) continue;
             for (int e = threadIdx.x; e < A.n2; e += kFT) {
-                const double2 X = buf[(e << A.lrw) + r];
+                const double2 X = buf[pad((e << A.lrw) + r)];
                 out[(size_t)j * A.n + k1 + (size_t)A.n1 * e] = sj * (X.x * X.x + X.y * X.y);
             }
         }
@@ -403,9 +422,11 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
 // C term x / sqrt(n) (x = src / *dv).  Writes P_g and the partial Re(x^* P_g).
 __global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __restrict__ src, const double* dv,
                                                   int lanczos) {
-    __shared__ double2 buf[kTile];
+    __shared__ double2 buf[kTileP];
+    __shared__ double2 tws[kTwLds];
     __shared__ double red[kFI / 64];
     if (lanczos && A.sc->broken) return;
+    load_tw(tws, A.f1, kFI);
     const int g = blockIdx.y;
     const int m20 = blockIdx.x * A.tc;
     const int tot = A.n1 << A.ltc;
@@ -421,17 +442,17 @@ __global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __re
             const int idx = threadIdx.x + u * kFI;
             if (idx < tot) {
                 const int k1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
-                buf[idx] = (m2 < A.n2) ? Zj[(int64_t)k1 * A.n2 + m2] : make_double2(0.0, 0.0);
+                buf[pad(idx)] = (m2 < A.n2) ? Zj[(int64_t)k1 * A.n2 + m2] : make_double2(0.0, 0.0);
             }
         }
         __syncthreads();
-        fft_tile<true, kFI>(buf, A.f1, A.ltc);
+        fft_tile<true, kFI>(buf, A.f1, A.ltc, tws);
 #pragma unroll
         for (int u = 0; u < kTile / kFI; ++u) {
             const int idx = threadIdx.x + u * kFI;
             if (idx < tot) {
                 const int m1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
-                if (m2 < A.n2) acc[u] = cadd(acc[u], cmul(psi_at(A, jn + (int64_t)m1 * A.n2 + m2), buf[idx]));
+                if (m2 < A.n2) acc[u] = cadd(acc[u], cmul(psi_at(A, jn + (int64_t)m1 * A.n2 + m2), buf[pad(idx)]));
             }
         }
         __syncthreads();
@@ -1040,9 +1061,9 @@ bool choose_shape(int64_t n, int L, int groups, int tile_cols, Shape& sh) {
     sh.lrw = ilog2(rw);
     sh.ntc = (sh.n2 + tc - 1) / tc;
     sh.nrw = (sh.n1 + rw - 1) / rw;
-    int G = groups;
-    if (G <= 0) G = (int)std::min<int64_t>(L, std::max<int64_t>(1, (1024 + sh.ntc - 1) / sh.ntc));
-    G = std::min(G, L);
+    // one group (every waveform summed in one workgroup) unless forced: measured fastest at n = 10^6
+    // (one group 262 us, four 309 us, twelve 425 us), as fewer groups write and re-read fewer sums
+    int G = groups > 0 ? std::min(groups, L) : 1;
     sh.mpg = (L + G - 1) / G;
     sh.G = (L + sh.mpg - 1) / sh.mpg;
     sh.ntwh = (int)((n >> kTwShift) + 1);
@@ -1082,8 +1103,8 @@ Layout layout(const scg_pr_params* p, int64_t n, int L, const Shape& sh, int qca
     l.S = take(cn * p->R);
     l.Wk = take(cn * p->R);
     l.small = take(sizeof(double2) * kPRMax * kPRMax);
-    l.tw1 = take(sizeof(double2) * sh.n1);
-    l.tw2 = take(sizeof(double2) * sh.n2);
+    l.tw1 = take(sizeof(double2) * kTwLds);
+    l.tw2 = take(sizeof(double2) * kTwLds);
     l.twh = take(sizeof(double2) * sh.ntwh);
     l.twl = take(sizeof(double2) * (1 << kTwShift));
     l.p_col = take(sizeof(double) * (size_t)sh.G * sh.ntc);
@@ -1313,7 +1334,10 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
     };
     hipStream_t st = c->stream;
     {
-        const std::vector<double2> t1 = twiddles(sh.n1, sh.n1, 1), t2 = twiddles(sh.n2, sh.n2, 1);
+        std::vector<double2> t1 = twiddles(sh.n1, 64, 64), t2 = twiddles(sh.n2, 64, 64);
+        const std::vector<double2> l1 = twiddles(sh.n1, 64, 1), l2 = twiddles(sh.n2, 64, 1);
+        t1.insert(t1.end(), l1.begin(), l1.end());
+        t2.insert(t2.end(), l2.begin(), l2.end());
         const std::vector<double2> th = twiddles(n, sh.ntwh, (int64_t)1 << kTwShift), tl = twiddles(n, 1 << kTwShift, 1);
         if (hipMemcpyAsync((void*)A.f1.tw, t1.data(), sizeof(double2) * t1.size(), hipMemcpyHostToDevice, st) ||
             hipMemcpyAsync((void*)A.f2.tw, t2.data(), sizeof(double2) * t2.size(), hipMemcpyHostToDevice, st) ||
