@@ -244,6 +244,9 @@ struct Radix<5, INV> {
 // read before the barrier and written after it.
 template <int R, bool INV, int NT>
 __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, const double2* tws) {
+    // j / Ns as a multiply-high: floor(j m / 2^32) with m = floor(2^32 / Ns) + 1 (2^32 / Ns for a
+    // power of two) equals floor(j / Ns) for every j, Ns <= 4096
+    const uint32_t mag = (Ns > 1) ? 0xFFFFFFFFu / (uint32_t)Ns + 1u : 0u;
     constexpr int MB = (kTile / NT + R - 1) / R;
     const int nseq = 1 << lns;
     const int nb = N / R;
@@ -256,7 +259,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int lns, int Ns, c
         const int bb = threadIdx.x + u * NT;
         if (bb < total) {
             const int s = bb & (nseq - 1), j = bb >> lns;
-            const int jq = j / Ns;
+            const int jq = (Ns > 1) ? (int)__umulhi((uint32_t)j, mag) : j;
             const int k = j - jq * Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -329,9 +332,16 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
     __syncthreads();
     fft_tile<false, kFT>(buf, A.f1, A.ltc, tws);
     double2* Yj = A.Y + (size_t)j * A.n;
-    for (int idx = threadIdx.x; idx < tot; idx += kFT) {
-        const int k1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
-        if (m2 < A.n2) Yj[(int64_t)k1 * A.n2 + m2] = cmul(buf[pad(idx)], twn(A, (int64_t)k1 * m2));
+    // this thread's outputs share m2 and step k1 by kFT / tc: w_n^{k1 m2} = w_n^{k1_0 m2} (w_n^{(kFT / tc) m2})^u
+    const int m2 = m20 + (threadIdx.x & (A.tc - 1));
+    const int k1_0 = threadIdx.x >> A.ltc;
+    if (m2 < A.n2 && k1_0 < A.n1) {
+        double2 w = twn(A, (int64_t)k1_0 * m2);
+        const double2 ws = twn(A, ((int64_t)(kFT >> A.ltc) * m2) % A.n);
+        for (int idx = threadIdx.x; idx < tot; idx += kFT) {
+            Yj[(int64_t)(idx >> A.ltc) * A.n2 + m2] = cmul(buf[pad(idx)], w);
+            w = cmul(w, ws);
+        }
     }
 }
 
@@ -368,11 +378,15 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
         fft_tile<true, kFT>(buf, A.f2, A.lrw, tws);
         for (int r = 0; r < A.rw; ++r) {
             const int k1 = k10 + r;
-            if (k1 >= A.n1) continue;
+            if (k1 >= A.n1 || (int)threadIdx.x >= A.n2) continue;
+            // conj(w_n^{k1 e}) for e = tid + kFT u: the first one times conj(w_n^{k1 kFT})^u
+            double2 w = twn(A, (int64_t)k1 * threadIdx.x);
+            double2 ws = twn(A, ((int64_t)k1 * kFT) % A.n);
+            w.y = -w.y;
+            ws.y = -ws.y;
             for (int e = threadIdx.x; e < A.n2; e += kFT) {
-                double2 w = twn(A, (int64_t)k1 * e);
-                w.y = -w.y;
                 Yj[(int64_t)k1 * A.n2 + e] = cmul(buf[pad((e << A.lrw) + r)], w);
+                w = cmul(w, ws);
             }
         }
     } else if (MODE == 1) {
