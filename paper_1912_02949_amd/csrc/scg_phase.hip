@@ -364,15 +364,26 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
         for (int e = threadIdx.x; e < A.n2; e += kFT)
             buf[pad((e << A.lrw) + r)] = (k1 < A.n1) ? Yj[(int64_t)k1 * A.n2 + e] : make_double2(0.0, 0.0);
     }
+    // the dual weights of this thread's tile positions p = tid + kFT u (row p & (rw - 1), entry
+    // p >> lrw), loaded before the forward transform so their latency overlaps it
+    constexpr int kPT = kTile / kFT;
+    double cw[kPT];
+    if (MODE == 0) {
+        const double* cj = A.c + (size_t)j * A.n;
+#pragma unroll
+        for (int u = 0; u < kPT; ++u) {
+            const int p = threadIdx.x + u * kFT;
+            const int k1 = k10 + (p & (A.rw - 1));
+            cw[u] = (p < (A.n2 << A.lrw) && k1 < A.n1) ? cj[(int64_t)k1 * A.n2 + (p >> A.lrw)] : 0.0;
+        }
+    }
     __syncthreads();
     fft_tile<false, kFT>(buf, A.f2, A.lrw, tws);
     if (MODE == 0) {
-        const double* cj = A.c + (size_t)j * A.n;
-        for (int r = 0; r < A.rw; ++r) {
-            const int k1 = k10 + r;
-            if (k1 >= A.n1) continue;
-            for (int e = threadIdx.x; e < A.n2; e += kFT) buf[pad((e << A.lrw) + r)] = cscl(buf[pad((e << A.lrw) + r)],
-                                                                                      cj[(int64_t)k1 * A.n2 + e]);
+#pragma unroll
+        for (int u = 0; u < kPT; ++u) {
+            const int p = threadIdx.x + u * kFT;
+            if (p < (A.n2 << A.lrw)) buf[pad(p)] = cscl(buf[pad(p)], cw[u]);
         }
         __syncthreads();
         fft_tile<true, kFT>(buf, A.f2, A.lrw, tws);
