@@ -83,7 +83,7 @@ struct PrArgs {
     const double2* psi;       // L x n (when the waveforms are stored whole)
     const uint8_t* psic;      // L x n dictionary codes (when they take at most 256 values)
     const double2* dict;      // the dictionary
-    int coded;
+    int coded, ndict;
     const double* s;          // L
     const double* b;          // L x n, row-pass order
     double* z;
@@ -126,9 +126,14 @@ __device__ __forceinline__ double2 mi(double2 x) {
 // bank groups also when a pass stores its outputs R or Ns values apart.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
 
-// psi_j(m): from the dictionary codes or the stored waveforms.
-__device__ __forceinline__ double2 psi_at(const PrArgs& A, size_t jm) {
-    return A.coded ? A.dict[A.psic[jm]] : A.psi[jm];
+// psi_j(m): from the dictionary codes (dl: the dictionary staged in LDS) or the stored waveforms.
+__device__ __forceinline__ double2 psi_at(const PrArgs& A, const double2* dl, size_t jm) {
+    return A.coded ? dl[A.psic[jm]] : A.psi[jm];
+}
+
+__device__ __forceinline__ void load_dict(double2* dl, const PrArgs& A, int nt) {
+    if (A.coded)
+        for (int i = threadIdx.x; i < A.ndict; i += nt) dl[i] = A.dict[i];
 }
 
 // Sum over an NT-thread workgroup (fixed order); red holds NT / 64 doubles.
@@ -310,6 +315,7 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
                                                   int lanczos) {
     __shared__ double2 buf[kTileP];
     __shared__ double2 tws[kTwLds];
+    __shared__ double2 dl[256];
     if (lanczos && A.sc->broken) return;
     const int j = blockIdx.y;
     const int m20 = blockIdx.x * A.tc;
@@ -317,6 +323,8 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
     const int tot = A.n1 << A.ltc;
     const size_t jn = (size_t)j * A.n;
     load_tw(tws, A.f1, kFT);
+    load_dict(dl, A, kFT);
+    __syncthreads();
     for (int idx = threadIdx.x; idx < tot; idx += kFT) {
         const int m1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
         double2 val = make_double2(0.0, 0.0);
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
             double2 x = src[m];
             x.x /= d;
             x.y /= d;
-            val = cmulc(x, psi_at(A, jn + m));
+            val = cmulc(x, psi_at(A, dl, jn + m));
         }
         buf[pad(idx)] = val;
     }
@@ -449,9 +457,11 @@ __global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __re
                                                   int lanczos) {
     __shared__ double2 buf[kTileP];
     __shared__ double2 tws[kTwLds];
+    __shared__ double2 dl[256];
     __shared__ double red[kFI / 64];
     if (lanczos && A.sc->broken) return;
     load_tw(tws, A.f1, kFI);
+    load_dict(dl, A, kFI);
     const int g = blockIdx.y;
     const int m20 = blockIdx.x * A.tc;
     const int tot = A.n1 << A.ltc;
@@ -462,12 +472,15 @@ __global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __re
     for (int j = j0; j < j1; ++j) {
         const double2* Zj = A.Y + (size_t)j * A.n;
         const size_t jn = (size_t)j * A.n;
+        int code[kTile / kFI];   // the waveform codes of this thread's outputs, loaded with the tile
 #pragma unroll
         for (int u = 0; u < kTile / kFI; ++u) {
             const int idx = threadIdx.x + u * kFI;
+            code[u] = 0;
             if (idx < tot) {
                 const int k1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
                 buf[pad(idx)] = (m2 < A.n2) ? Zj[(int64_t)k1 * A.n2 + m2] : make_double2(0.0, 0.0);
+                if (A.coded && m2 < A.n2) code[u] = A.psic[jn + (int64_t)k1 * A.n2 + m2];
             }
         }
         __syncthreads();
@@ -477,7 +490,10 @@ __global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __re
             const int idx = threadIdx.x + u * kFI;
             if (idx < tot) {
                 const int m1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
-                if (m2 < A.n2) acc[u] = cadd(acc[u], cmul(psi_at(A, jn + (int64_t)m1 * A.n2 + m2), buf[pad(idx)]));
+                if (m2 < A.n2) {
+                    const double2 ps = A.coded ? dl[code[u]] : A.psi[jn + (int64_t)m1 * A.n2 + m2];
+                    acc[u] = cadd(acc[u], cmul(ps, buf[pad(idx)]));
+                }
             }
         }
         __syncthreads();
@@ -1318,6 +1334,7 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
     A.psic = (const uint8_t*)(w + l.psic);
     A.dict = (const double2*)(w + l.dict);
     A.coded = 0;
+    A.ndict = 0;
     A.s = (const double*)(w + l.s);
     A.b = (const double*)(w + l.b);
     A.z = (double*)(w + l.z);
@@ -1400,6 +1417,7 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
     // (compared bitwise), else whole
     {
         bool coded = false;
+        int ndict = 0;
         if (p->mask_format == 0) {
             std::vector<double2> h((size_t)n * L);
             if (hipMemcpyAsync(h.data(), psi, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, st) ||
@@ -1422,6 +1440,7 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
                 }
                 codes[i] = (uint8_t)k;
             }
+            ndict = (int)dict.size();
             if (coded) {
                 if (hipMemcpyAsync((void*)A.psic, codes.data(), codes.size(), hipMemcpyHostToDevice, st) ||
                     hipMemcpyAsync((void*)A.dict, dict.data(), sizeof(double2) * dict.size(), hipMemcpyHostToDevice,
@@ -1432,6 +1451,7 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
         }
         A.psi = (const double2*)(w + l.psi);
         A.coded = coded ? 1 : 0;
+        A.ndict = coded ? ndict : 0;
         if (!coded && hipMemcpyAsync((void*)A.psi, psi, sizeof(double2) * (size_t)n * L, hipMemcpyDeviceToDevice, st))
             return fail(SCG_EHIP);
     }
