@@ -560,7 +560,14 @@ def main():
         print(json.dumps({"phase_sweep": phase_sweep(torch)}), flush=True)
         return
     if args.phase_only:
-        print(json.dumps({"phase_retrieval": phase_leg(torch, args.phase_T)}), flush=True)
+        ph = phase_leg(torch, args.phase_T)
+        # a 256 MiB device copy: calibrates FETCH_SIZE / WRITE_SIZE when this runs under rocprofv3 --pmc
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"phase_retrieval": ph, "copy_bytes": 4 * a.numel()}), flush=True)
         return
 
     norm_b = math.sqrt(float((inst.b * inst.b).sum()))

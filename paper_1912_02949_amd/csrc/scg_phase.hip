@@ -126,9 +126,12 @@ __device__ __forceinline__ double2 mi(double2 x) {
 // bank groups also when a pass stores its outputs R or Ns values apart.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
 
-// psi_j(m): from the dictionary codes (dl: the dictionary staged in LDS) or the stored waveforms.
-__device__ __forceinline__ double2 psi_at(const PrArgs& A, const double2* dl, size_t jm) {
-    return A.coded ? dl[A.psic[jm]] : A.psi[jm];
+// psi_j(m) for tile value idx of column tile `tile`: from the dictionary codes, stored tile by tile
+// (codes of waveform j, tile t, value idx = m1 tc + c at j * ntc * n1 * tc + t * n1 * tc + idx, so a
+// tile reads whole cache lines; dl: the dictionary staged in LDS), or the stored waveform at j n + m.
+__device__ __forceinline__ double2 psi_at(const PrArgs& A, const double2* dl, int j, int tile, int idx, int64_t m) {
+    return A.coded ? dl[A.psic[((size_t)j * A.ntc + tile) * ((size_t)A.n1 << A.ltc) + idx]]
+                   : A.psi[(size_t)j * A.n + m];
 }
 
 __device__ __forceinline__ void load_dict(double2* dl, const PrArgs& A, int nt) {
@@ -317,11 +320,14 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
     __shared__ double2 tws[kTwLds];
     __shared__ double2 dl[256];
     if (lanczos && A.sc->broken) return;
-    const int j = blockIdx.y;
-    const int m20 = blockIdx.x * A.tc;
+    // one-dimensional grid of ntc * L work items (padded to a multiple of 8): XCD x takes a contiguous
+    // range of them, all L waveforms of a column tile in a row, so the tile of x stays in its L2
+    const int wi = xcd_lid();
+    if (wi >= A.ntc * A.L) return;
+    const int tile = wi / A.L, j = wi - tile * A.L;
+    const int m20 = tile * A.tc;
     const double d = *dv;
     const int tot = A.n1 << A.ltc;
-    const size_t jn = (size_t)j * A.n;
     load_tw(tws, A.f1, kFT);
     load_dict(dl, A, kFT);
     __syncthreads();
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
             double2 x = src[m];
             x.x /= d;
             x.y /= d;
-            val = cmulc(x, psi_at(A, dl, jn + m));
+            val = cmulc(x, psi_at(A, dl, j, tile, idx, m));
         }
         buf[pad(idx)] = val;
     }
@@ -480,7 +486,8 @@ __global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __re
             if (idx < tot) {
                 const int k1 = idx >> A.ltc, m2 = m20 + (idx & (A.tc - 1));
                 buf[pad(idx)] = (m2 < A.n2) ? Zj[(int64_t)k1 * A.n2 + m2] : make_double2(0.0, 0.0);
-                if (A.coded && m2 < A.n2) code[u] = A.psic[jn + (int64_t)k1 * A.n2 + m2];
+                if (A.coded && m2 < A.n2)
+                    code[u] = A.psic[((size_t)j * A.ntc + blockIdx.x) * ((size_t)A.n1 << A.ltc) + idx];
             }
         }
         __syncthreads();
@@ -958,6 +965,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_round(int64_t n, const double2* u
 // ------------------------------------------------------------------ host helpers
 using cd = std::complex<double>;
 
+// Workgroups of the column pass: ntc * L work items, rounded up to a multiple of 8 (XCD renumbering).
+int colfwd_grid(const PrArgs& A) { return ((A.ntc * A.L + kXcd - 1) / kXcd) * kXcd; }
+
 // Radices of a 2,3,5-smooth N (8 first, then 4, 2, 5, 3); false if N has another factor.
 bool radix_plan(int N, std::vector<int>& r) {
     r.clear();
@@ -1129,7 +1139,7 @@ Layout layout(const scg_pr_params* p, int64_t n, int L, const Shape& sh, int qca
     };
     const size_t cn = sizeof(double2) * (size_t)n, rn = sizeof(double) * (size_t)n;
     l.psi = take(cn * L);
-    l.psic = take((size_t)n * L);
+    l.psic = take((size_t)sh.ntc * sh.n1 * sh.tc * L);
     l.dict = take(sizeof(double2) * 256);
     l.s = take(sizeof(double) * kPLMax);
     l.b = take(rn * L);
@@ -1212,7 +1222,7 @@ scg_status host_reduce(scg_pr_ctx* c, const double* dev, int parts, int w, std::
 // the partials of v^* D v in p_col.
 void enqueue_apply(scg_pr_ctx* c, const double2* src, const double* dv, int lanczos) {
     PrArgs& A = c->A;
-    hipLaunchKernelGGL(k_pr_colfwd, dim3(A.ntc, A.L), dim3(kFT), 0, c->stream, A, src, dv, lanczos);
+    hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, c->stream, A, src, dv, lanczos);
     hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, c->stream, A, lanczos, 0.0, (double*)nullptr);
     hipLaunchKernelGGL(k_pr_colinv, dim3(A.ntc, A.G), dim3(kFI), 0, c->stream, A, src, dv, lanczos);
 }
@@ -1245,7 +1255,7 @@ void enqueue_iteration(scg_pr_ctx* c, int t) {
     hipLaunchKernelGGL(k_pr_tridiag, dim3(1), dim3(kBlock), 0, st, A, q);
     hipLaunchKernelGGL(k_pr_ritz, dim3(gn), dim3(kBlock), 0, st, A);
     hipLaunchKernelGGL(k_pr_xnorm, dim3(1), dim3(kBlock), 0, st, A, gn);
-    hipLaunchKernelGGL(k_pr_colfwd, dim3(A.ntc, A.L), dim3(kFT), 0, st, A, (const double2*)A.xr, &A.sc->xnorm, 0);
+    hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, st, A, (const double2*)A.xr, &A.sc->xnorm, 0);
     hipLaunchKernelGGL(k_pr_row<1>, dim3(A.nrw, A.L), dim3(kFT), 0, st, A, 0, eta, (double*)nullptr);
     hipLaunchKernelGGL(k_pr_scalars, dim3(1), dim3(kBlock), 0, st, A, t, q, A.nrw * A.L, gL, beta, eta);
     hipLaunchKernelGGL(k_pr_dual, dim3(gL), dim3(kBlock), 0, st, A);
@@ -1424,7 +1434,8 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
                 hipStreamSynchronize(st))
                 return fail(SCG_EHIP);
             std::vector<double2> dict;
-            std::vector<uint8_t> codes(h.size());
+            const size_t tile_vals = (size_t)sh.n1 * sh.tc;
+            std::vector<uint8_t> codes((size_t)L * sh.ntc * tile_vals, 0);
             coded = true;
             for (size_t i = 0; i < h.size() && coded; ++i) {
                 int k = 0;
@@ -1438,7 +1449,11 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
                     }
                     dict.push_back(h[i]);
                 }
-                codes[i] = (uint8_t)k;
+                {   // waveform j, m = m1 n2 + m2 -> tile m2 / tc, value m1 tc + m2 % tc
+                    const size_t jj = i / (size_t)n, m = i - jj * (size_t)n;
+                    const size_t m1 = m / (size_t)sh.n2, m2 = m - m1 * (size_t)sh.n2;
+                    codes[(jj * sh.ntc + m2 / sh.tc) * tile_vals + m1 * sh.tc + (m2 % sh.tc)] = (uint8_t)k;
+                }
             }
             ndict = (int)dict.size();
             if (coded) {
@@ -1513,7 +1528,7 @@ scg_status scg_pr_apply(scg_pr_ctx* c, const double* w, const double* x, double*
 scg_status scg_pr_measure(scg_pr_ctx* c, const double* x, double* m) {
     if (!c || !x || !m) return SCG_EINVAL;
     PrArgs& A = c->A;
-    hipLaunchKernelGGL(k_pr_colfwd, dim3(A.ntc, A.L), dim3(kFT), 0, c->stream, A, (const double2*)x, &A.sc->one, 0);
+    hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, c->stream, A, (const double2*)x, &A.sc->one, 0);
     hipLaunchKernelGGL(k_pr_row<2>, dim3(A.nrw, A.L), dim3(kFT), 0, c->stream, A, 0, 0.0, m);
     PR_HIP(hipGetLastError());
     PR_HIP(hipStreamSynchronize(c->stream));
@@ -1750,7 +1765,7 @@ scg_status scg_pr_time_apply(scg_pr_ctx* c, int32_t reps, double* ms) {
     enqueue_apply(c, v, dv, 0);   // warm-up
     PR_HIP(hipEventRecord(ev[0], st));
     for (int r = 0; r < reps; ++r)
-        hipLaunchKernelGGL(k_pr_colfwd, dim3(A.ntc, A.L), dim3(kFT), 0, st, A, v, dv, 0);
+        hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, st, A, v, dv, 0);
     PR_HIP(hipEventRecord(ev[1], st));
     for (int r = 0; r < reps; ++r)
         hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, st, A, 0, 0.0, (double*)nullptr);
