@@ -433,6 +433,24 @@ def phase_bytes(n: int, L: int, G: int, psi_bytes: int) -> dict:
             "colinv": (16 + psi_bytes) * L * n + 16 * n * (1 + G)}
 
 
+PHASE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_traffic_cdp_1m_fp64.json")
+
+
+def phase_traffic() -> dict:
+    """Counted HBM bytes per launch of the three passes, when the profile matches the current source."""
+    try:
+        doc = json.load(open(PHASE_TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return {}
+    with open(os.path.join(ROOT, "paper_1912_02949_amd", "csrc", "scg_phase.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if doc.get("phase_source_sha") != sha:
+        return {}
+    return {"colfwd": doc["passes"]["k_pr_colfwd"]["hbm_bytes_per_launch"],
+            "row": doc["passes"]["k_pr_row<0>"]["hbm_bytes_per_launch"],
+            "colinv": doc["passes"]["k_pr_colinv"]["hbm_bytes_per_launch"]}
+
+
 def phase_sweep(torch) -> list:
     """Per-pass times of the n = 10^6 product for several column-tile widths and waveform groups."""
     import synth.phase as sp
@@ -472,10 +490,11 @@ def phase_leg(torch, T: int) -> dict:
     products = sum(q + 1 for q in qs)      # q Lanczos products and the measurement pass per iteration
     byt = phase_bytes(n, L, info["mask_groups"], 1 if info["mask_codes"] else 16)
     passes = {}
+    counted = phase_traffic() if (info["n1"], info["n2"], info["mask_groups"]) == (250, 4000, 1) else {}
     for key in ("colfwd", "row", "colinv"):
         gbs = byt[key] / (tm[key] * 1e-3) / 1e9
         passes[key] = {"avg_us": tm[key] * 1e3, "algorithmic_bytes": byt[key], "achieved_GBps": gbs,
-                       "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+                       "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "traffic": counted.get(key)}
     tot = sum(byt.values())
     out = {"workload": "phase retrieval SDP, coded diffraction patterns, n = 10^6, L = 12 (d = 12n), R = 5, "
                        "alpha = 3n, FP64 complex, first %d iterations" % T,
