@@ -451,6 +451,40 @@ def phase_traffic() -> dict:
             "colinv": doc["passes"]["k_pr_colinv"]["hbm_bytes_per_launch"]}
 
 
+def phase_accuracy(torch, sizes, T: int) -> list:
+    """Relative error of the rounded signal (Section 7.3.3) against solve time, at checkpoints.
+    The reconstruction and rounding at a checkpoint are not part of the solve time."""
+    import synth.phase as sp
+    from paper_1912_02949_amd.api import PhaseParams, PhaseRetrieval
+    out = []
+    for n in sizes:
+        k = int(round(math.log10(n)))
+        inst = sp.coded_diffraction(n, sp.PHASE_SEEDS.get(k, 0x5C6A5000 + k), L=12)
+        s = PhaseRetrieval(inst.psi, inst.b, PhaseParams(R=5, T=T, seed=0x5C6A5000 + k))
+        pts, t_done, solve_s = [], 0, 0.0
+        marks = sorted({c for c in (50, 100, 200, 300, 500, 700, 1000, 1500, 2000, 3000, 4000, 5000, 7000,
+                                    10000, 15000, 20000) if c <= T} | {T})
+        for cp in marks:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(cp - t_done)
+            s.synchronize()
+            solve_s += time.perf_counter() - t0
+            t_done = cp
+            if s.get_state()["tau"] == 0.0:
+                rel = 1.0          # X = 0 so far (every H was 0): the rounded signal is 0
+            else:
+                U, lam, _ = s.reconstruct()
+                _, rel = s.round(U, lam, inst.chi)
+            pts.append({"t": cp, "rel_error": rel, "solve_s": solve_s})
+            progress(f"phase accuracy n={n} t={cp}: relative error {rel:.3e}, {solve_s:.2f} s")
+            if rel < 1e-3:
+                break
+        out.append({"n": n, "points": pts})
+        del s
+    return out
+
+
 def phase_sweep(torch) -> list:
     """Per-pass times of the n = 10^6 product for several column-tile widths and waveform groups."""
     import synth.phase as sp
@@ -522,6 +556,9 @@ def main():
     ap.add_argument("--no-storage-optimal", action="store_true")
     ap.add_argument("--phase-T", type=int, default=30, help="iterations of the phase retrieval leg (0: skip)")
     ap.add_argument("--phase-only", action="store_true", help="only the phase retrieval leg")
+    ap.add_argument("--phase-accuracy", type=str, default="",
+                    help="only the relative error of the rounded signal against solve time, for these comma-separated n")
+    ap.add_argument("--phase-accuracy-T", type=int, default=5000)
     ap.add_argument("--phase-sweep", action="store_true",
                     help="only per-pass times of the phase retrieval product over tile widths and waveform groups")
     ap.add_argument("--probe-workload", type=int, default=2, choices=(2, 3, 5),
@@ -575,6 +612,10 @@ def main():
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
         return
 
+    if args.phase_accuracy:
+        sizes = [int(float(v)) for v in args.phase_accuracy.split(",")]
+        print(json.dumps({"phase_accuracy": phase_accuracy(torch, sizes, args.phase_accuracy_T)}), flush=True)
+        return
     if args.phase_sweep:
         print(json.dumps({"phase_sweep": phase_sweep(torch)}), flush=True)
         return
