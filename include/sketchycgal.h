@@ -430,12 +430,16 @@ typedef struct {
     int32_t  instance;      /* Philox counter word                                        */
     int32_t  mask_groups;   /* inverse column pass: the waveforms are split into this many
                                groups, each summed by its own workgroups into its own
-                               partial product; 0 = one group, else 1 .. L                 */
+                               partial product; 0 = chosen at init (with autotune = 1 one
+                               product is timed for 1, 2, 3, 4, 6, 12 and L groups and the
+                               fastest kept, a later candidate only when at least 3% faster;
+                               with autotune = 0 one group), else 1 .. L                   */
     int32_t  tile_cols;     /* columns per column-pass tile: 0 = chosen, else a power of
                                two with n1 * tile_cols <= 4096                             */
     int32_t  mask_format;   /* 0: waveforms stored as one-byte codes into a dictionary when
                                they take at most 256 distinct values (bitwise; the coded
                                diffraction waveforms take 8), else whole; 1: always whole */
+    int32_t  autotune;      /* 1: choose mask_groups by timing at init (when it is 0)      */
 } scg_pr_params;
 
 /* Summary in ORIGINAL units: objective tr X, infeasibility ||A X - b||. */

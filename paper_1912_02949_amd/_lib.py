@@ -48,6 +48,7 @@ class scg_pr_params(C.Structure):
         ("alpha", C.c_double), ("seed", C.c_uint64), ("q_mode", C.c_int32), ("q_fixed", C.c_int32),
         ("scale", C.c_int32), ("trace_correct", C.c_int32), ("instance", C.c_int32),
         ("mask_groups", C.c_int32), ("tile_cols", C.c_int32), ("mask_format", C.c_int32),
+        ("autotune", C.c_int32),
     ]
 
 

@@ -354,6 +354,7 @@ class PhaseParams:
     mask_groups: int = 0          # inverse column pass: waveform groups (0: chosen)
     tile_cols: int = 0            # column-pass tile width (0: chosen)
     mask_format: int = 0          # 0: dictionary codes when the waveforms take <= 256 values; 1: whole
+    autotune: int = 1             # 1: time the waveform group counts at init when mask_groups = 0
 
     def to_c(self) -> _lib.scg_pr_params:
         p = _lib.scg_pr_params()

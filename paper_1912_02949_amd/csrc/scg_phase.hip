@@ -1076,6 +1076,7 @@ struct Layout {
 
 struct Shape {
     int n1, n2, tc, ltc, rw, lrw, G, mpg, ntc, nrw, ntwh;
+    int Gmax;   // the most waveform groups the workspace holds (every candidate of the init tuner)
 };
 
 int ilog2(int x) {
@@ -1117,6 +1118,7 @@ bool choose_shape(int64_t n, int L, int groups, int tile_cols, Shape& sh) {
     int G = groups > 0 ? std::min(groups, L) : 1;
     sh.mpg = (L + G - 1) / G;
     sh.G = (L + sh.mpg - 1) / sh.mpg;
+    sh.Gmax = groups > 0 ? sh.G : L;
     sh.ntwh = (int)((n >> kTwShift) + 1);
     return true;
 }
@@ -1147,7 +1149,7 @@ Layout layout(const scg_pr_params* p, int64_t n, int L, const Shape& sh, int qca
     l.y = take(rn * L);
     l.c = take(rn * L);
     l.Y = take(cn * L);
-    l.P = take(cn * sh.G);
+    l.P = take(cn * sh.Gmax);
     l.V = take(cn * (size_t)(qcap + 1));
     l.xr = take(cn);
     l.Om = take(cn * p->R);
@@ -1158,7 +1160,7 @@ Layout layout(const scg_pr_params* p, int64_t n, int L, const Shape& sh, int qca
     l.tw2 = take(sizeof(double2) * kTwLds);
     l.twh = take(sizeof(double2) * sh.ntwh);
     l.twl = take(sizeof(double2) * (1 << kTwShift));
-    l.p_col = take(sizeof(double) * (size_t)sh.G * sh.ntc);
+    l.p_col = take(sizeof(double) * (size_t)sh.Gmax * sh.ntc);
     l.p_upd = take(sizeof(double) * kGU);
     l.p_meas = take(sizeof(double) * 3 * (size_t)L * sh.nrw);
     l.p_prep = take(sizeof(double) * kGU);
@@ -1185,6 +1187,7 @@ bool params_ok(const scg_pr_params* p, int64_t n, int L) {
     if (p->mask_groups < 0 || p->mask_groups > L) return false;
     if (p->tile_cols < 0) return false;
     if (p->mask_format != 0 && p->mask_format != 1) return false;
+    if (p->autotune != 0 && p->autotune != 1) return false;
     if (L < 1 || L > kPLMax) return false;
     if (qmax_for(p, n) > kPQCap) return false;
     return true;
@@ -1273,6 +1276,53 @@ void enqueue_iteration(scg_pr_ctx* c, int t) {
     else hipLaunchKernelGGL(k_pr_skupd<16>, dim3(gn), dim3(kBlock), 0, st, A, eta);
 }
 
+// Waveform groups of the inverse column pass, chosen at init: one product D v (after a warm-up one)
+// timed with HIP events for G in {1, 2, 3, 4, 6, 12, L} (as far as they differ and fit L), the fastest
+// kept; a later candidate replaces the best so far only when at least 3% faster.  The operands are the
+// first iteration's dual weights and start vector, which the first iteration forms again.
+scg_status tune_groups(scg_pr_ctx* c) {
+    PrArgs& A = c->A;
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_pr_prep, dim3(grid_for((int64_t)A.L * A.n)), dim3(kBlock), 0, st, A,
+                       c->prm.beta0 * std::sqrt(2.0));
+    const int gh = grid_for((A.n + 1) / 2);
+    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, (uint64_t)1,
+                       (uint64_t)c->prm.instance, 1);
+    hipLaunchKernelGGL(k_pr_norm, dim3(1), dim3(kBlock), 0, st, A, 0, gh, 0);
+    hipEvent_t e0, e1;
+    PR_HIP(hipEventCreate(&e0));
+    PR_HIP(hipEventCreate(&e1));
+    int best_g = -1, best_mpg = 0;
+    float best_ms = 0.f;
+    std::vector<int> seen;
+    for (int cand : {1, 2, 3, 4, 6, 12, A.L}) {
+        if (cand > A.L) continue;
+        const int mpg = (A.L + cand - 1) / cand;
+        const int G = (A.L + mpg - 1) / mpg;
+        if (std::find(seen.begin(), seen.end(), G) != seen.end()) continue;
+        seen.push_back(G);
+        A.G = G;
+        A.mpg = mpg;
+        enqueue_apply(c, A.V, &A.sc->nrm[0], 0);
+        PR_HIP(hipEventRecord(e0, st));
+        enqueue_apply(c, A.V, &A.sc->nrm[0], 0);
+        PR_HIP(hipEventRecord(e1, st));
+        PR_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        PR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (best_g < 0 || ms < 0.97f * best_ms) {
+            best_g = G;
+            best_mpg = mpg;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    A.G = best_g;
+    A.mpg = best_mpg;
+    return hipGetLastError() == hipSuccess ? SCG_OK : SCG_EHIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1293,6 +1343,7 @@ void scg_pr_default_params(scg_pr_params* p) {
     p->mask_groups = 0;
     p->tile_cols = 0;
     p->mask_format = 0;
+    p->autotune = 1;
 }
 
 scg_status scg_pr_workspace_size(const scg_pr_params* p, int64_t n, int32_t L, size_t* bytes) {
@@ -1496,6 +1547,10 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
                            (uint64_t)p->seed, (uint64_t)p->instance);
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return fail(SCG_EHIP);
+    if (p->mask_groups == 0 && p->autotune && L > 1) {
+        const scg_status ts = tune_groups(c);
+        if (ts != SCG_OK) return fail(ts);
+    }
     *out = c;
     return SCG_OK;
 }

@@ -225,10 +225,12 @@ def test_validation_errors_and_nonfinite_flag():
     assert e.value.status == SCG_EINVAL
     inst = coded_diffraction(64, 1, L=3)
     for bad in (dict(R=17), dict(R=0), dict(T=0), dict(beta0=-1.0), dict(tile_cols=3), dict(mask_groups=4),
-                dict(mask_format=2)):
+                dict(mask_format=2), dict(autotune=2)):
         with pytest.raises(SCGError) as e:
             make(inst, **{**dict(R=2, T=2), **bad})
         assert e.value.status == SCG_EINVAL, bad
+    assert make(inst, R=2, T=2, autotune=0).summary()["mask_groups"] == 1
+    assert 1 <= make(inst, R=2, T=2).summary()["mask_groups"] <= 3
     s = make(inst, R=2, T=3)
     s.step(3)
     with pytest.raises(SCGError) as e:
