@@ -472,7 +472,8 @@ def phase_accuracy(torch, sizes, T: int) -> list:
     for n in sizes:
         k = int(round(math.log10(n)))
         inst = sp.coded_diffraction(n, sp.PHASE_SEEDS.get(k, 0x5C6A5000 + k), L=12)
-        s = PhaseRetrieval(inst.psi, inst.b, PhaseParams(R=5, T=T, seed=0x5C6A5000 + k))
+        st = torch.cuda.Stream()   # a non-null stream: iterations replay captured graphs
+        s = PhaseRetrieval(inst.psi, inst.b, PhaseParams(R=5, T=T, seed=0x5C6A5000 + k), stream=st)
         pts, t_done, solve_s = [], 0, 0.0
         marks = sorted({c for c in (50, 100, 200, 300, 500, 700, 1000, 1500, 2000, 3000, 4000, 5000, 7000,
                                     10000, 15000, 20000) if c <= T} | {T})
@@ -523,7 +524,7 @@ def phase_leg(torch, T: int) -> dict:
     n, L = 10 ** 6, 12
     inst = sp.coded_diffraction(n, sp.PHASE_SEEDS[6], L=L)
     prm = PhaseParams(R=5, T=T, seed=sp.PHASE_SEEDS[6])
-    s = PhaseRetrieval(inst.psi, inst.b, prm)
+    s = PhaseRetrieval(inst.psi, inst.b, prm, stream=torch.cuda.Stream())   # graph replays
     info = s.summary()
     tm = s.time_apply(20)
     torch.cuda.synchronize()

@@ -478,7 +478,11 @@ scg_status scg_pr_workspace_size(const scg_pr_params* p, int64_t n, int32_t L, s
 scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int32_t L, const double* psi,
                        const double* b, const double* omega, void* workspace, size_t bytes, void* stream);
 
-/* Enqueue `iters` iterations (asynchronous).  SCG_ESTATE past T. */
+/* Enqueue `iters` iterations (asynchronous).  SCG_ESTATE past T.  On a
+ * non-null stream runs of iterations with the same Lanczos step count replay
+ * one HIP graph per count (captured on first use, owned by the context; the
+ * kernels read t from a device counter); on the null stream the kernels are
+ * launched one by one.  Both give bit-identical results. */
 scg_status scg_pr_step(scg_pr_ctx* ctx, int32_t iters);
 
 /* y = (C + A^*(w)) x in scaled units: w device double[L*n] (dual weights,

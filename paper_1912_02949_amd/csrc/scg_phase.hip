@@ -30,6 +30,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "../../include/sketchycgal.h"
@@ -71,7 +72,7 @@ struct PrScalars {
     double coef[kPQCap];             // eigenvector of T_k
     double dots[2 * kPRMax];         // v^* Omega of the normalised Ritz vector
     double xi, ha, xnorm, p, tau, gamma, one;
-    int k, broken, flags, pad;
+    int k, broken, flags, t_iter;    // t_iter: the iteration counter read by a replayed graph
 };
 
 struct PrArgs {
@@ -120,6 +121,15 @@ template <bool INV>
 __device__ __forceinline__ double2 mi(double2 x) {
     return INV ? make_double2(-x.y, x.x) : make_double2(x.y, -x.x);
 }
+
+// Iteration t of a launch: the argument, or (t = 0, a replayed graph) the device counter; beta_t and
+// eta_t from it as the host computes them.
+__device__ __forceinline__ int pr_t(const PrArgs& A, int t) { return t > 0 ? t : A.sc->t_iter; }
+__device__ __forceinline__ double pr_beta(const PrArgs& A, int t) { return A.beta0 * sqrt(t + 1.0); }
+__device__ __forceinline__ double pr_eta(int t) { return 2.0 / (t + 1.0); }
+
+__global__ void k_pr_set_t(PrScalars* sc, int t) { sc->t_iter = t; }
+__global__ void k_pr_advance_t(PrScalars* sc) { sc->t_iter += 1; }
 
 // LDS position of tile value i: one padding value after every eight, so that
 // the eight lanes a 16-byte LDS access serves per cycle fall into distinct
@@ -364,7 +374,7 @@ __global__ __launch_bounds__(kFT) void k_pr_colfwd(PrArgs A, const double2* __re
 // values m = s_j |X|^2 update z <- (1 - eta) z + eta ha m, with partial sums of
 // ||z - b||^2, <y, z - b>, ||y||^2.  MODE 2: m written to out in natural order.
 template <int MODE>
-__global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double eta, double* out) {
+__global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, int tt, double* out) {
     __shared__ double2 buf[kTileP];
     __shared__ double2 tws[kTwLds];
     __shared__ double red[kFT / 64];
@@ -415,6 +425,7 @@ __global__ __launch_bounds__(kFT) void k_pr_row(PrArgs A, int lanczos, double et
             }
         }
     } else if (MODE == 1) {
+        const double eta = pr_eta(pr_t(A, tt));
         const double sj = A.s[j];
         const double eh = eta * A.sc->ha;
         const double keep = 1.0 - eta;
@@ -532,7 +543,8 @@ __global__ __launch_bounds__(kFI) void k_pr_colinv(PrArgs A, const double2* __re
 // ------------------------------------------------------------------ Lanczos
 // Start vector of iteration t: complex element m is the Box-Muller pair
 // (2m, 2m + 1) of the Philox stream (seed; t, instance, purpose 2).
-__global__ __launch_bounds__(kBlock) void k_pr_start(PrArgs A, uint64_t seed, uint64_t t, uint64_t inst, int q) {
+__global__ __launch_bounds__(kBlock) void k_pr_start(PrArgs A, uint64_t seed, int tt, uint64_t inst, int q) {
+    const uint64_t t = (uint64_t)pr_t(A, tt);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         A.sc->broken = 0;
         A.sc->k = q;
@@ -668,7 +680,8 @@ __global__ __launch_bounds__(kBlock) void k_pr_xnorm(PrArgs A, int nparts) {
 
 // ------------------------------------------------------------------ state updates
 // Start of iteration t: c = s_j (y + beta (z - b)) and partials of <w, z>.
-__global__ __launch_bounds__(kBlock) void k_pr_prep(PrArgs A, double beta) {
+__global__ __launch_bounds__(kBlock) void k_pr_prep(PrArgs A, int tt) {
+    const double beta = pr_beta(A, pr_t(A, tt));
     double acc = 0.0;
     const int64_t tot = (int64_t)A.L * A.n;
     for (int64_t pos = blockIdx.x * (int64_t)kBlock + threadIdx.x; pos < tot; pos += (int64_t)gridDim.x * kBlock) {
@@ -684,8 +697,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_prep(PrArgs A, double beta) {
 
 // Scalars of the iteration: gap, p, tau, gamma (dual step size, eqn
 // sketchy-cgal-dual-step with ||A|| = 1, the K guard), and the log record.
-__global__ __launch_bounds__(kBlock) void k_pr_scalars(PrArgs A, int t, int q, int nmeas, int nprep, double beta,
-                                                      double eta) {
+__global__ __launch_bounds__(kBlock) void k_pr_scalars(PrArgs A, int tt, int q, int nmeas, int nprep) {
+    const int t = pr_t(A, tt);
+    const double beta = pr_beta(A, t), eta = pr_eta(t);
     double m3[3], wz[1];
     reduce_partials<3>(A.p_meas, nmeas, m3);
     reduce_partials<1>(A.p_prep, nprep, wz);
@@ -775,7 +789,8 @@ __global__ __launch_bounds__(kBlock) void k_pr_skred(PrArgs A, int nparts) {
 
 // S <- (1 - eta) S + eta ha v (v^* Omega).
 template <int RB>
-__global__ __launch_bounds__(kBlock) void k_pr_skupd(PrArgs A, double eta) {
+__global__ __launch_bounds__(kBlock) void k_pr_skupd(PrArgs A, int tt) {
+    const double eta = pr_eta(pr_t(A, tt));
     double2 dt[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) dt[c] = (c < A.R) ? make_double2(A.sc->dots[2 * c], A.sc->dots[2 * c + 1])
@@ -1065,6 +1080,7 @@ struct scg_pr_ctx {
     double2* small;                  // R x R matrices for the reconstruction
     double* p_red;                   // host-reduced partials
     int nred;
+    std::map<int, hipGraphExec_t> graphs;   // captured iterations by Lanczos step count (non-null streams)
 };
 
 namespace {
@@ -1226,7 +1242,7 @@ scg_status host_reduce(scg_pr_ctx* c, const double* dev, int parts, int w, std::
 void enqueue_apply(scg_pr_ctx* c, const double2* src, const double* dv, int lanczos) {
     PrArgs& A = c->A;
     hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, c->stream, A, src, dv, lanczos);
-    hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, c->stream, A, lanczos, 0.0, (double*)nullptr);
+    hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, c->stream, A, lanczos, 0, (double*)nullptr);
     hipLaunchKernelGGL(k_pr_colinv, dim3(A.ntc, A.G), dim3(kFI), 0, c->stream, A, src, dv, lanczos);
 }
 
@@ -1237,15 +1253,16 @@ int q_of(const scg_pr_ctx* c, int t) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(q, std::min<int64_t>(c->n - 1, c->qcap)));
 }
 
-void enqueue_iteration(scg_pr_ctx* c, int t) {
+// One iteration with q Lanczos steps.  With dev the kernels take t (and beta_t, eta_t) from the device
+// counter: the form captured into a graph and replayed for every iteration with the same q; otherwise t
+// is the launch argument.
+void enqueue_iteration(scg_pr_ctx* c, int t_host, int q, bool dev) {
     PrArgs& A = c->A;
     hipStream_t st = c->stream;
-    const double beta = c->prm.beta0 * std::sqrt(t + 1.0);
-    const double eta = 2.0 / (t + 1.0);
-    const int q = q_of(c, t);
+    const int t = dev ? 0 : t_host;
     const int gL = grid_for((int64_t)A.L * A.n), gn = grid_for(A.n), gh = grid_for((A.n + 1) / 2);
-    hipLaunchKernelGGL(k_pr_prep, dim3(gL), dim3(kBlock), 0, st, A, beta);
-    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, (uint64_t)t,
+    hipLaunchKernelGGL(k_pr_prep, dim3(gL), dim3(kBlock), 0, st, A, t);
+    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, t,
                        (uint64_t)c->prm.instance, q);
     hipLaunchKernelGGL(k_pr_norm, dim3(1), dim3(kBlock), 0, st, A, 0, gh, 0);
     for (int i = 0; i < q; ++i) {
@@ -1259,8 +1276,8 @@ void enqueue_iteration(scg_pr_ctx* c, int t) {
     hipLaunchKernelGGL(k_pr_ritz, dim3(gn), dim3(kBlock), 0, st, A);
     hipLaunchKernelGGL(k_pr_xnorm, dim3(1), dim3(kBlock), 0, st, A, gn);
     hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, st, A, (const double2*)A.xr, &A.sc->xnorm, 0);
-    hipLaunchKernelGGL(k_pr_row<1>, dim3(A.nrw, A.L), dim3(kFT), 0, st, A, 0, eta, (double*)nullptr);
-    hipLaunchKernelGGL(k_pr_scalars, dim3(1), dim3(kBlock), 0, st, A, t, q, A.nrw * A.L, gL, beta, eta);
+    hipLaunchKernelGGL(k_pr_row<1>, dim3(A.nrw, A.L), dim3(kFT), 0, st, A, 0, t, (double*)nullptr);
+    hipLaunchKernelGGL(k_pr_scalars, dim3(1), dim3(kBlock), 0, st, A, t, q, A.nrw * A.L, gL);
     hipLaunchKernelGGL(k_pr_dual, dim3(gL), dim3(kBlock), 0, st, A);
     const int R = A.R;
     if (R <= 1) hipLaunchKernelGGL(k_pr_skdot<1>, dim3(gn), dim3(kBlock), 0, st, A);
@@ -1269,11 +1286,54 @@ void enqueue_iteration(scg_pr_ctx* c, int t) {
     else if (R <= 8) hipLaunchKernelGGL(k_pr_skdot<8>, dim3(gn), dim3(kBlock), 0, st, A);
     else hipLaunchKernelGGL(k_pr_skdot<16>, dim3(gn), dim3(kBlock), 0, st, A);
     hipLaunchKernelGGL(k_pr_skred, dim3(1), dim3(kBlock), 0, st, A, gn);
-    if (R <= 1) hipLaunchKernelGGL(k_pr_skupd<1>, dim3(gn), dim3(kBlock), 0, st, A, eta);
-    else if (R <= 2) hipLaunchKernelGGL(k_pr_skupd<2>, dim3(gn), dim3(kBlock), 0, st, A, eta);
-    else if (R <= 4) hipLaunchKernelGGL(k_pr_skupd<4>, dim3(gn), dim3(kBlock), 0, st, A, eta);
-    else if (R <= 8) hipLaunchKernelGGL(k_pr_skupd<8>, dim3(gn), dim3(kBlock), 0, st, A, eta);
-    else hipLaunchKernelGGL(k_pr_skupd<16>, dim3(gn), dim3(kBlock), 0, st, A, eta);
+    if (R <= 1) hipLaunchKernelGGL(k_pr_skupd<1>, dim3(gn), dim3(kBlock), 0, st, A, t);
+    else if (R <= 2) hipLaunchKernelGGL(k_pr_skupd<2>, dim3(gn), dim3(kBlock), 0, st, A, t);
+    else if (R <= 4) hipLaunchKernelGGL(k_pr_skupd<4>, dim3(gn), dim3(kBlock), 0, st, A, t);
+    else if (R <= 8) hipLaunchKernelGGL(k_pr_skupd<8>, dim3(gn), dim3(kBlock), 0, st, A, t);
+    else hipLaunchKernelGGL(k_pr_skupd<16>, dim3(gn), dim3(kBlock), 0, st, A, t);
+}
+
+// The captured iteration for Lanczos step count q (instantiated on first use, cached in the context).
+hipError_t graph_for(scg_pr_ctx* c, int q, hipGraphExec_t* out) {
+    auto f = c->graphs.find(q);
+    if (f != c->graphs.end()) {
+        *out = f->second;
+        return hipSuccess;
+    }
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    enqueue_iteration(c, 0, q, true);
+    hipLaunchKernelGGL(k_pr_advance_t, dim3(1), dim3(1), 0, c->stream, c->A.sc);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    c->graphs[q] = ge;
+    *out = ge;
+    return hipSuccess;
+}
+
+// Runs of iterations with the same q_t replay one captured iteration, after a one-thread kernel has set
+// the device counter to the run's first t.
+scg_status step_graphs(scg_pr_ctx* c, int32_t iters) {
+    int k = 0;
+    while (k < iters) {
+        const int t = c->t_next;
+        const int q = q_of(c, t);
+        int m = 1;
+        while (k + m < iters && q_of(c, t + m) == q) ++m;
+        hipGraphExec_t ge = nullptr;
+        PR_HIP(graph_for(c, q, &ge));
+        hipLaunchKernelGGL(k_pr_set_t, dim3(1), dim3(1), 0, c->stream, c->A.sc, t);
+        PR_HIP(hipGetLastError());
+        for (int j = 0; j < m; ++j) PR_HIP(hipGraphLaunch(ge, c->stream));
+        c->t_next += m;
+        k += m;
+    }
+    return SCG_OK;
 }
 
 // Waveform groups of the inverse column pass, chosen at init: one product D v (after a warm-up one)
@@ -1283,10 +1343,9 @@ void enqueue_iteration(scg_pr_ctx* c, int t) {
 scg_status tune_groups(scg_pr_ctx* c) {
     PrArgs& A = c->A;
     hipStream_t st = c->stream;
-    hipLaunchKernelGGL(k_pr_prep, dim3(grid_for((int64_t)A.L * A.n)), dim3(kBlock), 0, st, A,
-                       c->prm.beta0 * std::sqrt(2.0));
+    hipLaunchKernelGGL(k_pr_prep, dim3(grid_for((int64_t)A.L * A.n)), dim3(kBlock), 0, st, A, 1);
     const int gh = grid_for((A.n + 1) / 2);
-    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, (uint64_t)1,
+    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, 1,
                        (uint64_t)c->prm.instance, 1);
     hipLaunchKernelGGL(k_pr_norm, dim3(1), dim3(kBlock), 0, st, A, 0, gh, 0);
     hipEvent_t e0, e1;
@@ -1557,6 +1616,8 @@ scg_status scg_pr_init(scg_pr_ctx** out, const scg_pr_params* p, int64_t n, int3
 
 scg_status scg_pr_destroy(scg_pr_ctx* c) {
     if (!c) return SCG_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     delete c;
     return SCG_OK;
 }
@@ -1564,7 +1625,11 @@ scg_status scg_pr_destroy(scg_pr_ctx* c) {
 scg_status scg_pr_step(scg_pr_ctx* c, int32_t iters) {
     if (!c || iters < 0) return SCG_EINVAL;
     if (c->t_next + iters - 1 > c->prm.T) return SCG_ESTATE;
-    for (int i = 0; i < iters; ++i) enqueue_iteration(c, c->t_next++);
+    if (c->stream != nullptr) return step_graphs(c, iters);
+    for (int i = 0; i < iters; ++i) {
+        enqueue_iteration(c, c->t_next, q_of(c, c->t_next), false);
+        ++c->t_next;
+    }
     return hipGetLastError() == hipSuccess ? SCG_OK : SCG_EHIP;
 }
 
@@ -1584,7 +1649,7 @@ scg_status scg_pr_measure(scg_pr_ctx* c, const double* x, double* m) {
     if (!c || !x || !m) return SCG_EINVAL;
     PrArgs& A = c->A;
     hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, c->stream, A, (const double2*)x, &A.sc->one, 0);
-    hipLaunchKernelGGL(k_pr_row<2>, dim3(A.nrw, A.L), dim3(kFT), 0, c->stream, A, 0, 0.0, m);
+    hipLaunchKernelGGL(k_pr_row<2>, dim3(A.nrw, A.L), dim3(kFT), 0, c->stream, A, 0, 0, m);
     PR_HIP(hipGetLastError());
     PR_HIP(hipStreamSynchronize(c->stream));
     return SCG_OK;
@@ -1807,10 +1872,9 @@ scg_status scg_pr_time_apply(scg_pr_ctx* c, int32_t reps, double* ms) {
     hipStream_t st = c->stream;
     const int t = std::min(c->t_next, c->prm.T);
     // valid operands: the dual weights of iteration t and its start vector in V[0]
-    hipLaunchKernelGGL(k_pr_prep, dim3(grid_for((int64_t)A.L * A.n)), dim3(kBlock), 0, st, A,
-                       c->prm.beta0 * std::sqrt(t + 1.0));
+    hipLaunchKernelGGL(k_pr_prep, dim3(grid_for((int64_t)A.L * A.n)), dim3(kBlock), 0, st, A, t);
     const int gh = grid_for((A.n + 1) / 2);
-    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, (uint64_t)t,
+    hipLaunchKernelGGL(k_pr_start, dim3(gh), dim3(kBlock), 0, st, A, (uint64_t)c->prm.seed, t,
                        (uint64_t)c->prm.instance, 1);
     hipLaunchKernelGGL(k_pr_norm, dim3(1), dim3(kBlock), 0, st, A, 0, gh, 0);
     const double2* v = A.V;
@@ -1823,7 +1887,7 @@ scg_status scg_pr_time_apply(scg_pr_ctx* c, int32_t reps, double* ms) {
         hipLaunchKernelGGL(k_pr_colfwd, dim3(colfwd_grid(A)), dim3(kFT), 0, st, A, v, dv, 0);
     PR_HIP(hipEventRecord(ev[1], st));
     for (int r = 0; r < reps; ++r)
-        hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, st, A, 0, 0.0, (double*)nullptr);
+        hipLaunchKernelGGL(k_pr_row<0>, dim3(A.nrw, A.L), dim3(kFT), 0, st, A, 0, 0, (double*)nullptr);
     PR_HIP(hipEventRecord(ev[2], st));
     for (int r = 0; r < reps; ++r)
         hipLaunchKernelGGL(k_pr_colinv, dim3(A.ntc, A.G), dim3(kFI), 0, st, A, v, dv, 0);

@@ -119,6 +119,42 @@ def test_trajectory_matches_oracle(name, n, L, kw):
     assert abs(summ["infeasibility"] - ref.infeasibility) < 1e-9 * ref.infeasibility
 
 
+@pytest.mark.parametrize("n,kw", [(64, dict(R=5, T=40, seed=7, autotune=0)),
+                                  (4800, dict(R=4, T=24, seed=5, beta0=4.0, autotune=0))])
+def test_graph_replays_match_eager_launches(n, kw):
+    """On a non-null stream step() replays one captured iteration per Lanczos step count; the results
+    equal the eager launches of the null stream bit for bit, whatever the chunks step() is called with.
+    (The waveform groups are fixed: timing at init could pick a different count, and so a different
+    summation order, for each context.)"""
+    need_gpu()
+    import torch
+    from paper_1912_02949_amd.api import PhaseParams, PhaseRetrieval
+    inst = coded_diffraction(n, 123, L=12)
+    eager = make(inst, **kw)
+    eager.run()
+    st = torch.cuda.Stream()
+    announce(f"phase graph replays n={n}")
+    g = PhaseRetrieval(inst.psi, inst.b, PhaseParams(**kw), stream=st)
+    done = 0
+    for chunk in (7, 13, 20):
+        m = min(chunk, kw["T"] - done)
+        if m <= 0:
+            break
+        g.step(m)
+        done += m
+    if done < kw["T"]:
+        g.step(kw["T"] - done)
+    g.synchronize()
+    assert eager.summary()["mask_groups"] == g.summary()["mask_groups"]
+    le, lg = eager.log(), g.log()
+    for key in ("t", "q", "k", "xi", "p", "infeas", "gamma", "gap", "beta", "eta"):
+        assert np.array_equal(le[key], lg[key]), key
+    se, sg = eager.get_state(), g.get_state()
+    for key in ("z", "y", "S"):
+        assert torch.equal(se[key], sg[key]), key
+    assert se["p"] == sg["p"] and se["tau"] == sg["tau"]
+
+
 def test_one_iteration_from_injected_state():
     need_gpu()
     n, L = 64, 12
