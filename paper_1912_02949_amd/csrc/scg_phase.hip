@@ -1129,8 +1129,8 @@ bool choose_shape(int64_t n, int L, int groups, int tile_cols, Shape& sh) {
     sh.lrw = ilog2(rw);
     sh.ntc = (sh.n2 + tc - 1) / tc;
     sh.nrw = (sh.n1 + rw - 1) / rw;
-    // one group (every waveform summed in one workgroup) unless forced: measured fastest at n = 10^6
-    // (one group 262 us, four 309 us, twelve 425 us), as fewer groups write and re-read fewer sums
+    // one group (every waveform summed in one workgroup) unless forced or tuned at init: at n = 10^6 one
+    // group takes 130 us, four 157, twelve 215 (fewer groups write and re-read fewer sums)
     int G = groups > 0 ? std::min(groups, L) : 1;
     sh.mpg = (L + G - 1) / G;
     sh.G = (L + sh.mpg - 1) / sh.mpg;

@@ -49,6 +49,7 @@ def oracle_params(**kw):
 
 
 SHAPES = [
+    (5, 3, {}),                                 # n1 = 1, n2 = 5
     (64, 12, {}),                               # n1 = 1
     (1000, 12, {}),
     (4800, 12, {}),                             # n1 = 2, n2 = 2400
