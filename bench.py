@@ -516,14 +516,14 @@ def phase_sweep(torch) -> list:
     return rows
 
 
-def phase_leg(torch, T: int) -> dict:
+def phase_leg(torch, T: int, groups: int = 0) -> dict:
     """Phase retrieval at the paper's largest size (n = 10^6, 12 coded diffraction patterns, R = 5,
     alpha = 3n, FP64): T iterations timed as a whole, and the three passes of the D v product."""
     import synth.phase as sp
     from paper_1912_02949_amd.api import PhaseParams, PhaseRetrieval
     n, L = 10 ** 6, 12
     inst = sp.coded_diffraction(n, sp.PHASE_SEEDS[6], L=L)
-    prm = PhaseParams(R=5, T=T, seed=sp.PHASE_SEEDS[6])
+    prm = PhaseParams(R=5, T=T, seed=sp.PHASE_SEEDS[6], mask_groups=groups)
     s = PhaseRetrieval(inst.psi, inst.b, prm, stream=torch.cuda.Stream())   # graph replays
     info = s.summary()
     tm = s.time_apply(20)
@@ -569,6 +569,9 @@ def main():
     ap.add_argument("--no-storage-optimal", action="store_true")
     ap.add_argument("--phase-T", type=int, default=30, help="iterations of the phase retrieval leg (0: skip)")
     ap.add_argument("--phase-only", action="store_true", help="only the phase retrieval leg")
+    ap.add_argument("--phase-groups", type=int, default=0,
+                    help="waveform groups of the phase retrieval leg (0: tuned at init; the counter passes fix 1, "
+                         "since timing under counter collection is not representative)")
     ap.add_argument("--phase-accuracy", type=str, default="",
                     help="only the relative error of the rounded signal against solve time, for these comma-separated n")
     ap.add_argument("--phase-accuracy-T", type=int, default=5000)
@@ -633,7 +636,7 @@ def main():
         print(json.dumps({"phase_sweep": phase_sweep(torch)}), flush=True)
         return
     if args.phase_only:
-        ph = phase_leg(torch, args.phase_T)
+        ph = phase_leg(torch, args.phase_T, args.phase_groups)
         # a 256 MiB device copy: calibrates FETCH_SIZE / WRITE_SIZE when this runs under rocprofv3 --pmc
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)

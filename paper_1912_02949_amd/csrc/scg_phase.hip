@@ -22,8 +22,16 @@
 //                                        the group's waveforms, + v / sqrt(n),
 //                                        partial v^* D v
 // The DFTs are mixed-radix Stockham passes (radices 8, 4, 2, 5, 3) on a tile
-// of at most 4096 complex values in LDS, each pass staging its butterflies
-// in registers between two barriers (so one buffer suffices).
+// of at most 4096 complex values in LDS (one padding value after every eight,
+// so no pass has bank conflicts), each pass staging its butterflies in
+// registers between two barriers (so one buffer suffices), with the stage
+// twiddles from a 128-value two-level table in LDS.  The forward passes run
+// 512 threads per workgroup (two workgroups per CU), the inverse column pass
+// 1024 (its per-thread sums in registers).  Waveforms that take at most 256
+// values are stored as one-byte codes, tile by tile, into a dictionary staged
+// in LDS.  The forward column pass is one-dimensional and XCD-mapped: all L
+// waveforms of a column tile run in a row on one XCD, which keeps that tile of
+// the vector in its L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1075,11 +1083,9 @@ struct scg_pr_ctx {
     double alpha0, c_F, opnorm;
     std::vector<double> s;
     int t_next;
-    std::vector<double2> tw1, tw2;   // host copies (for the plans)
     double2* Wk;                     // R x n reconstruction work array
     double2* small;                  // R x R matrices for the reconstruction
     double* p_red;                   // host-reduced partials
-    int nred;
     std::map<int, hipGraphExec_t> graphs;   // captured iterations by Lanczos step count (non-null streams)
 };
 
