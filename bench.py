@@ -58,15 +58,17 @@ PROBE_SHAPES = {
     5: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)),
 }
 TRAFFIC_FILES = {
-    2: os.path.join(ROOT, "profiles", "spmv_traffic_torus_1m_fp32.json"),
-    3: os.path.join(ROOT, "profiles", "spmv_traffic_powerlaw_4m_fp32.json"),
-    5: os.path.join(ROOT, "profiles", "spmv_traffic_geometric_8m_fp32.json"),
+    (2, "fp32"): os.path.join(ROOT, "profiles", "spmv_traffic_torus_1m_fp32.json"),
+    (3, "fp32"): os.path.join(ROOT, "profiles", "spmv_traffic_powerlaw_4m_fp32.json"),
+    (5, "fp32"): os.path.join(ROOT, "profiles", "spmv_traffic_geometric_8m_fp32.json"),
+    (5, "fp64"): os.path.join(ROOT, "profiles", "spmv_traffic_geometric_8m_fp64.json"),
 }
 
 
-def measured_traffic(k: int, summ: dict):
-    """HBM bytes per SpMV launch of the shape in `summ`, from the committed counter summary of workload k."""
-    path = TRAFFIC_FILES.get(k)
+def measured_traffic(k: int, summ: dict, precision: str = "fp32"):
+    """HBM bytes per SpMV launch of the shape in `summ`, from the committed counter summary of workload k
+    in that precision."""
+    path = TRAFFIC_FILES.get((k, precision))
     if path is None or not os.path.exists(path):
         return None
     with open(path) as f:
@@ -388,7 +390,7 @@ def spmv_roofline(solve, inst, precision: str, reps: int, k: int) -> dict:
             "algorithmic_bytes_per_product": by, "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
             "format_bytes_per_product": by_fmt, "format_GBps": by_fmt / (us * 1e-6) / 1e9,
             "gathers_per_s": nnz_off / (us * 1e-6),
-            "traffic": measured_traffic(k, summ) if precision == "fp32" else None}
+            "traffic": measured_traffic(k, summ, precision)}
 
 
 def solve_leg(torch, k: int, inst, precision: str, T: int, spmv_reps: int = 100, warm_T: int = 20) -> dict:
@@ -579,6 +581,8 @@ def main():
                     help="only per-pass times of the phase retrieval product over tile widths and waveform groups")
     ap.add_argument("--probe-workload", type=int, default=2, choices=(2, 3, 5),
                     help="workload of --traffic-probe")
+    ap.add_argument("--probe-precision", default="fp32", choices=("fp32", "fp64"),
+                    help="precision of --traffic-probe")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only the SpMV kernel, 20 launches in each shape the autotuner chooses from (lanes per "
                          "row x workgroups), for rocprofv3 --pmc, plus a 256 MiB device copy whose counters "
@@ -605,8 +609,8 @@ def main():
         pqs = qs if kp == 2 else q_schedule(100, pinst.n)
         shapes = []
         for lanes, grid, seg in PROBE_SHAPES[kp]:
-            prm = Params(R=10, T=100 if kp != 2 else T, seed=synth.CONFIG_SEEDS[kp], precision="fp32", autotune=0,
-                         segments=seg, spmv_lanes=lanes, spmv_grid=grid)
+            prm = Params(R=10, T=100 if kp != 2 else T, seed=synth.CONFIG_SEEDS[kp], precision=args.probe_precision,
+                         autotune=0, segments=seg, spmv_lanes=lanes, spmv_grid=grid)
             sp = Solve(pinst, prm, torch)
             sp.init()
             sp.lib.sketchycgal_step(sp.ctx, 2)
@@ -624,7 +628,7 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"workload": kp, "shapes": shapes, "copy_bytes": 4 * a.numel(),
+        print(json.dumps({"workload": kp, "precision": args.probe_precision, "shapes": shapes, "copy_bytes": 4 * a.numel(),
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
         return
 
@@ -759,6 +763,7 @@ def main():
         r64 = others["workload_5"]["fp64_spmv"]
         roofline["fp64"] = {"kernel": r64["kernel"] + " (workload 5 Lanczos SpMV, FP64)",
                             "achieved": r64["achieved_GBps"], "frac": r64["achieved_GBps"] / HBM_PEAK_GBS,
+                            "traffic": r64["traffic"],
                             "algorithmic_bytes_per_launch": r64["algorithmic_bytes_per_product"],
                             "avg_launch_us": r64["avg_product_us"]}
     value = args.steps * T / dt64
