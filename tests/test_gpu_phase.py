@@ -156,6 +156,26 @@ def test_graph_replays_match_eager_launches(n, kw):
     assert se["p"] == sg["p"] and se["tau"] == sg["tau"]
 
 
+def test_lanczos_breakdown_with_zero_measurements():
+    """b = 0: the dual weights vanish, D = C = I / sqrt(n) has one eigenvalue, and the recurrence breaks
+    down after one step in every iteration (reading R3: rho <= 64 eps (|omega| + rho_prev)); the oracle
+    does the same."""
+    need_gpu()
+    inst = coded_diffraction(64, 5)
+    b = np.zeros_like(inst.b)
+    kw = dict(R=3, T=4, seed=2, alpha=10.0)
+    from paper_1912_02949_amd.api import PhaseParams, PhaseRetrieval
+    s = PhaseRetrieval(inst.psi, b, PhaseParams(**kw))
+    s.run()
+    lg = s.log()
+    ref = sketchy_cgal_phase(inst.psi, b, oracle_params(**kw))
+    assert np.array_equal(lg["k"], ref.log["k"]) and (lg["k"] == 1).all()
+    assert (lg["flags"] & 1).all()
+    assert np.abs(lg["xi"] - 1.0 / 8.0).max() < 1e-14
+    assert np.array_equal(lg["gamma"], ref.log["gamma"]) and (lg["infeas"] == 0).all()
+    assert s.summary()["objective"] == 0.0
+
+
 def test_one_iteration_from_injected_state():
     need_gpu()
     n, L = 64, 12
