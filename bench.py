@@ -50,12 +50,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # SpMV shapes whose HBM traffic the profile records: (lanes per row, workgroups cap, column segments);
-# workgroups 0 = one row-block range per wave; lanes 1 = the quad-chunk product (k_spmvq); 8 segments = the
-# concurrent form (k_spmv slice sums + k_xcombine)
+# workgroups 0 = one row-block range per wave; lanes 1 = a chunk product (k_spmvq over padded column-word
+# quads; k_spmve over unpadded entries with their values); 8 segments = the concurrent form (k_spmv slice
+# sums + k_xcombine)
 PROBE_SHAPES = {
     2: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2), (1, 1536, 1), (1, 2048, 1)),
     3: ((2, 1024, 8), (2, 2048, 8), (4, 1536, 4), (4, 0, 1)),
-    5: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)),
+    5: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((1, 1536, 1), (1, 1792, 1), (1, 2048, 1)),
 }
 TRAFFIC_FILES = {
     (2, "fp32"): os.path.join(ROOT, "profiles", "spmv_traffic_torus_1m_fp32.json"),
@@ -84,10 +85,11 @@ KERNEL_SOURCES = ["scg_kernels.hpp", "scg_device.hpp", "scg_internal.hpp"]
 
 
 def spmv_kernel_name(summ: dict) -> str:
-    """The product kernel the autotuner chose: lanes 1 is the quad-chunk layout; with 8 column segments the
-    row-block kernel runs them in one launch and k_xcombine adds the segment sums."""
+    """The product kernel the autotuner chose: lanes 1 is a chunk layout (quad chunks of column words, or
+    entry chunks when values are stored); with 8 column segments the row-block kernel runs them in one launch
+    and k_xcombine adds the segment sums."""
     if summ["spmv_lanes"] == 1:
-        return "k_spmvq"
+        return "k_spmve" if summ["matrix_format"] == 0 else "k_spmvq"
     return "k_spmv + k_xcombine" if summ["spmv_segments"] == 8 else "k_spmv"
 
 

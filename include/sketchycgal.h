@@ -94,13 +94,15 @@ typedef struct {
                                XCD gathers from one eighth of x; their raw row sums go to a
                                workspace buffer and a second pass adds them up)               */
     int32_t  spmv_lanes;    /* lanes per row of the SpMV reduction: 0 = autotuned / by mean
-                               row length, or 2, 4, 8, 16, 32; 1 = the quad-chunk product
-                               (each row's column words padded to 16-byte quads, rows packed
-                               into chunks of 64 quads, one chunk per wave, rows summed by a
-                               lane scan): only for compressed formats (matrix_format 0 with
-                               one off-diagonal magnitude) and rows of at most 128
-                               off-diagonal entries, one column segment; init returns
-                               SCG_EINVAL when the matrix does not qualify                    */
+                               row length, or 2, 4, 8, 16, 32; 1 = a chunk product (one chunk
+                               of 256 entries per wave, 4 per lane, rows summed by a scan
+                               across the lanes): for compressed formats (one off-diagonal
+                               magnitude) the quad-chunk layout (each row's column words
+                               padded to 16-byte quads, rows of at most 128 off-diagonal
+                               entries); with stored values the entry-chunk layout (column
+                               words and values unpadded, a row starting anywhere in a quad,
+                               rows of at most 64 off-diagonal entries); one column segment;
+                               init returns SCG_EINVAL when the matrix does not qualify      */
     int32_t  spmv_grid;     /* SpMV workgroups: 0 = autotuned / one row-block range per wave,
                                or a cap (rounded to a multiple of 8, at most 2048)            */
     int32_t  basis_mode;    /* Lanczos basis storage: 0 = all q+1 vectors kept (ld x (q+1)),
@@ -162,8 +164,8 @@ typedef struct {
     double objective;         /* <C, X>                                     */
     double infeasibility;     /* ||diag X - b|| (box or ball: dist_K)       */
     double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
-    int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction (1: the
-                                 quad-chunk product)                                            */
+    int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction (1: a chunk
+                                 product, quad-chunk or entry-chunk by matrix_format)          */
     int32_t spmv_segments;    /* column segments of the SpMV (8: the concurrent form)          */
     int32_t matrix_format;    /* storage of the off-diagonal values: 0 values, 1 columns only
                                  (common value), 2 columns with sign bit (common magnitude)  */

@@ -43,17 +43,28 @@ int qmax_for(const scg_params& p, int64_t n) {
 
 size_t elem_size(const scg_params& p) { return p.precision == SCG_FP32_STREAM ? 4 : 8; }
 
-// Chunks of the quad-chunk SpMV layout to reserve (0: that layout is never
-// used with these parameters).  A row takes max(1, ceil(d / 4)) quads and
-// rows of at most kQRowMax entries (32 quads) are packed whole into chunks
-// of 64 quads; a chunk is closed only when the next row does not fit, so
-// every chunk but the last holds at least 33 quads.  The sum over rows is at
-// most nnz / 4 + n quads.
+// Chunks of the quad-chunk SpMV layout (column words) to reserve (0: that
+// layout is never used with these parameters).  A row takes max(1, ceil(d / 4))
+// quads and rows of at most kQRowMax entries (32 quads) are packed whole into
+// chunks of 64 quads; a chunk is closed only when the next row does not fit,
+// so every chunk but the last holds at least 33 quads.  The sum over rows is
+// at most nnz / 4 + n quads.
 int64_t quad_chunk_cap(const scg_params& p, int64_t n, int64_t nnz) {
     if (p.matrix_format == 1 || (p.spmv_lanes != 0 && p.spmv_lanes != 1) || p.segments > 1) return 0;
     if (n >= ((int64_t)1 << 29)) return 0;   // columns must fit the 29-bit field
     const int64_t dq = nnz / 4 + n + 1;
     return dq / 33 + 2;
+}
+
+// Chunks of the entry-chunk layout (values stored) to reserve.  A row takes
+// max(1, d) entries and rows of at most kERowMax entries are packed whole
+// into chunks of 256; a chunk is closed only when the next row does not fit,
+// so every chunk but the last holds at least 256 - kERowMax + 1 entries.  The
+// sum over rows is at most nnz + n entries.
+int64_t entry_chunk_cap(const scg_params& p, int64_t n, int64_t nnz) {
+    if ((p.spmv_lanes != 0 && p.spmv_lanes != 1) || p.segments > 1) return 0;
+    if (n >= ((int64_t)1 << 29)) return 0;
+    return (nnz + n) / (256 - kERowMax + 1) + 2;
 }
 
 // Column segments the SpMV may use with these parameters: kSegMax when the
@@ -66,8 +77,8 @@ int seg_cap(const scg_params& p, int64_t n, int64_t nnz) {
 }
 
 struct Layout {
-    size_t rp, col, val, dC, b, z, y, s, V, u, v, xp, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, qw, qc,
-        total;
+    size_t rp, col, val, dC, b, z, y, s, V, u, v, xp, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, qw, qv,
+        qc, total;
     size_t recon_bytes;
 };
 
@@ -106,9 +117,11 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.racc = take(p.basis_mode == 1 ? 8 * ld : 0);
     L.lo = take(p.constraint_set == 1 ? 8 * (size_t)n : 0);   // box constraint set, scaled
     L.hi = take(p.constraint_set == 1 ? 8 * (size_t)n : 0);
-    const int64_t nqc = quad_chunk_cap(p, n, nnz);
-    L.qw = take(sizeof(int32_t) * 256 * (size_t)nqc);
-    L.qc = take(sizeof(int2) * (size_t)nqc);
+    // the chunk layouts: column words for the larger of the two, values for the entry layout
+    const int64_t nqc = quad_chunk_cap(p, n, nnz), nec = entry_chunk_cap(p, n, nnz);
+    L.qw = take(sizeof(int32_t) * 256 * (size_t)std::max(nqc, nec));
+    L.qv = take(es * 256 * (size_t)nec);
+    L.qc = take(sizeof(int2) * (size_t)std::max(nqc, nec));
     L.total = off;
     return L;
 }
@@ -147,6 +160,7 @@ Prob<T> prob(scg_ctx* c) {
     P.rb = c->rb;
     P.nrb = c->nrb;
     P.qw = c->qw;
+    P.qv = (const T*)c->qv;
     P.qc = c->qc;
     P.nqc = c->nqc;
     P.sc = c->sc;
@@ -220,10 +234,12 @@ void launch_spmv_f(scg_ctx* c, const T* x, int step, int lanes) {
 template <typename T, int MODE>
 void launch_spmv(scg_ctx* c, const T* x, int step, int lanes = 0) {
     if (lanes == 0) lanes = c->lanes;
-    if (lanes == 1) {   // the quad-chunk product (column-word formats only)
+    if (lanes == 1) {   // the chunk products: padded column-word quads, or entries with values
         const dim3 g(c->Gs), b(kBlock);
         if (c->fmt == FMT_PAT) hipLaunchKernelGGL((k_spmvq<T, MODE, FMT_PAT>), g, b, 0, c->stream, prob<T>(c), x, step);
-        else hipLaunchKernelGGL((k_spmvq<T, MODE, FMT_SGN>), g, b, 0, c->stream, prob<T>(c), x, step);
+        else if (c->fmt == FMT_SGN)
+            hipLaunchKernelGGL((k_spmvq<T, MODE, FMT_SGN>), g, b, 0, c->stream, prob<T>(c), x, step);
+        else hipLaunchKernelGGL((k_spmve<T, MODE>), g, b, 0, c->stream, prob<T>(c), x, step);
         return;
     }
     if (c->fmt == FMT_PAT) launch_spmv_f<T, MODE, 8, FMT_PAT>(c, x, step, lanes);
@@ -689,6 +705,70 @@ scg_status build_quad_chunks(scg_ctx* c, const int64_t* row_ptr, const int32_t* 
     return SCG_OK;
 }
 
+// The entry-chunk layout: row r's off-diagonal entries (input order, diagonal
+// skipped, values scaled as k_scatter stores them) from entry eoff[r] on, the
+// first word flagged as the row's start; a row without off-diagonal entries
+// takes one padding entry flagged as a start.  The words and values of every
+// chunk were filled with padding (kQPad, 0) beforehand.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_entries(int64_t n, const int64_t* rp, const int32_t* col,
+                                                            const double* val, const int64_t* eoff, int32_t* qw,
+                                                            T* qv, double inv_cF) {
+    int64_t lo, hi;
+    split_range(n, xcd_lid(), gridDim.x, lo, hi);
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+        const int64_t o = eoff[r];
+        int64_t d = 0;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int32_t j = col[e];
+            if ((int64_t)j == r) continue;
+            qw[o + d] = (d == 0) ? (j | kQStart) : j;
+            qv[o + d] = (T)(val[e] * inv_cF);
+            ++d;
+        }
+        if (d == 0) qw[o] = kQPad | kQStart;
+    }
+}
+
+// Build the entry-chunk layout when the matrix qualifies (values stored, every
+// row at most kERowMax off-diagonal entries); cnt = off-diagonal entries per
+// row.  The entry offsets go through the basis area, unused yet.
+template <typename T>
+scg_status build_entry_chunks(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, const double* val,
+                              const std::vector<int32_t>& cnt) {
+    c->nqc = 0;
+    const int64_t n = c->n;
+    if (!c->qv || c->fmt != FMT_VAL) return SCG_OK;
+    for (int64_t r = 0; r < n; ++r)
+        if (cnt[r] > kERowMax) return SCG_OK;
+    std::vector<int64_t> eoff(n);
+    std::vector<int2> qc;
+    int fill = 256;
+    for (int64_t r = 0; r < n; ++r) {
+        const int d = std::max(1, (int)cnt[r]);
+        if (fill + d > 256) {
+            qc.push_back(make_int2((int)r, 0));
+            fill = 0;
+        }
+        eoff[r] = (int64_t)(qc.size() - 1) * 256 + fill;
+        fill += d;
+        qc.back().y = (fill + 3) / 4;
+    }
+    if ((int64_t)qc.size() > entry_chunk_cap(c->prm, n, c->nnz_in)) return SCG_OK;   // cannot happen (the bound)
+    const size_t slots = 256 * qc.size();
+    int64_t* deoff = reinterpret_cast<int64_t*>(c->V);
+    HIP_TRY(hipMemcpyAsync(deoff, eoff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->qc, qc.data(), sizeof(int2) * qc.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)c->qw, kQPad, slots, c->stream));
+    HIP_TRY(hipMemsetAsync(c->qv, 0, sizeof(T) * slots, c->stream));
+    hipLaunchKernelGGL((k_scatter_entries<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, row_ptr, col, val, deoff,
+                       c->qw, (T*)c->qv, 1.0 / c->c_F);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->nqc = (int64_t)qc.size();
+    return SCG_OK;
+}
+
 // Shift, start vector, the first product and the first update of iteration
 // `it` (its partial sums are what the timed step-1 products reduce).
 template <typename T>
@@ -696,6 +776,23 @@ void time_spmv_setup(scg_ctx* c, const IterArgs& it) {
     enqueue_prep<T>(c, it);
     launch_spmv<T, SPMV_LANCZOS>(c, basis_col<T>(c, 0), 0);
     hipLaunchKernelGGL((k_lupdate<T>), dim3(c->G), dim3(kBlock), 0, c->stream, prob<T>(c), 0, 1, 0);
+}
+
+// Workgroups of the chunk product that the device keeps resident at once (its
+// occupancy times the compute units), at most kGMax; 0 if the runtime cannot tell.
+template <typename T>
+int chunk_resident_grid(scg_ctx* c) {
+    int per_cu = 0, cus = 0;
+    hipError_t e;
+    if (c->fmt == FMT_VAL)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmve<T, SPMV_LANCZOS>, kBlock, 0);
+    else if (c->fmt == FMT_PAT)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmvq<T, SPMV_LANCZOS, FMT_PAT>, kBlock, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmvq<T, SPMV_LANCZOS, FMT_SGN>, kBlock, 0);
+    if (e != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+        return 0;
+    return std::min(kGMax, per_cu * cus / 8 * 8);
 }
 
 // Autotuner: time the Lanczos SpMV on this matrix for each lanes-per-row
@@ -773,11 +870,14 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         c->xseg = false;
         c->Gs = g_keep;
     }
-    // the quad-chunk product, when the matrix has that layout
+    // the chunk product, when the matrix has a chunk layout: 1536 or 2048 workgroups, or as many as
+    // the kernel's occupancy keeps resident
     if (c->nqc > 0 && (c->prm.spmv_lanes == 0 || c->prm.spmv_lanes == 1) && c->prm.segments <= 1) {
         const int g_keep = c->Gs;
-        for (int g : {1536, 2048}) {
+        const int g_res = chunk_resident_grid<T>(c);
+        for (int g : {1536, 2048, g_res}) {
             if (c->prm.spmv_grid > 0 && g != 1536) continue;   // a forced grid is applied afterwards
+            if (g == g_res && (g == 1536 || g == 2048 || g < 8)) continue;
             c->Gs = g;
             float ms = 0.f;
             HIP_TRY(time_lanes(1, ms));
@@ -876,7 +976,8 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
                        c->col, (T*)c->val, dCraw, c->dC, c->b, inv_cF, inv_alpha, c->fmt);
     HIP_TRY(hipGetLastError());
     {
-        scg_status st = build_quad_chunks<T>(c, row_ptr, col, val, hcnt);
+        scg_status st = (c->fmt == FMT_VAL) ? build_entry_chunks<T>(c, row_ptr, col, val, hcnt)
+                                            : build_quad_chunks<T>(c, row_ptr, col, val, hcnt);
         if (st != SCG_OK) return st;
     }
     if (c->lo) {   // K = {b} until sketchycgal_set_constraints
@@ -979,7 +1080,7 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (qmax_for(*p, n) + 1 > kQCap) return false;
     const int l = p->spmv_lanes;
     if (l != 0 && l != 1 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
-    if (l == 1 && (p->segments > 1 || p->matrix_format == 1)) return false;   // the quad-chunk product
+    if (l == 1 && p->segments > 1) return false;   // the chunk products
     if (p->segments != 0 && p->segments != 1 && p->segments != 2 && p->segments != 4 && p->segments != kSegMax)
         return false;
     if (p->spmv_grid < 0 || p->spmv_grid > kGMax) return false;
@@ -1077,8 +1178,10 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->logs = (scg_iter_log*)(base + L.logs);
     c->recon = (double*)(base + L.recon);
     c->recon_bytes = L.recon_bytes;
-    c->qc_cap = quad_chunk_cap(*p, n, nnz);
+    const int64_t nec = entry_chunk_cap(*p, n, nnz);
+    c->qc_cap = std::max(quad_chunk_cap(*p, n, nnz), nec);
     c->qw = (c->qc_cap > 0) ? (int32_t*)(base + L.qw) : nullptr;
+    c->qv = (nec > 0) ? (void*)(base + L.qv) : nullptr;
     c->qc = (c->qc_cap > 0) ? (int2*)(base + L.qc) : nullptr;
     c->nqc = 0;
     scg_status st = (p->precision == SCG_FP32_STREAM) ? init_typed<float>(c, row_ptr, col, val, b, omega)

@@ -75,7 +75,8 @@ struct Prob {
     T* S;                 // sketch, n x R column-major (column c at c*ld)
     const int32_t* rb;    // row-block boundaries, int32[nrb+1]
     int nrb;
-    const int32_t* qw;    // quad-chunk layout: column words, 64 quads per chunk
+    const int32_t* qw;    // chunk layouts: column words, 64 quads per chunk
+    const T* qv;          // entry-chunk layout: values beside the words
     const int2* qc;       // per chunk: (first row, quads used)
     int64_t nqc;          // chunks
     DevScalars* sc;
@@ -152,7 +153,10 @@ struct scg_ctx {
     double* lo;      // box constraint set, scaled (constraint_set = 1), else null
     double* hi;
     size_t recon_bytes;
-    int32_t* qw;     // quad-chunk layout of the off-diagonal columns (null when not reserved)
+    // chunk layouts of the off-diagonal entries: padded quads of column words (one
+    // off-diagonal magnitude) or unpadded entries with their values (values stored)
+    int32_t* qw;     // column words, 256 per chunk (null when not reserved)
+    void* qv;        // values of the entry-chunk layout, 256 per chunk (null when not reserved)
     int2* qc;        // per chunk: (first row, quads used)
     int64_t nqc;     // chunks built (0: the matrix does not qualify)
     int64_t qc_cap;  // chunks reserved

@@ -638,6 +638,165 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
     }
 }
 
+// The product over the entry-chunk layout (off-diagonal values stored, rows of
+// at most kERowMax entries).  The CSR entries, column word and value side by
+// side, are packed whole rows at a time into chunks of 256 entries (64 lanes x
+// one 16-byte quad each).  Rows are not padded: a row may start anywhere in a
+// quad, its first word flagged by kQStart; a row with no off-diagonal entry
+// holds one padding entry; padding entries (kQPad, value 0) complete the
+// chunk's last quad as part of its last row.  P.qc[c] = (first row, quads
+// used).  One wave takes one chunk at a time, one quad per lane:
+//   - four ballots of the start flags give each entry's row within the chunk
+//     and the chunk's row count; the gathers of x and the loads of x_r and the
+//     shift of the chunk's rows (one row per lane, coalesced) are issued
+//     together;
+//   - the lane sums its four products row by row, a segmented scan across the
+//     lanes carries the running sum of the row open at each lane's end, and
+//     the lane holding a row's last entry stores the row's sum in the wave's
+//     LDS slice;
+//   - one lane per row applies the shift and the scale exactly as k_spmv does
+//     and stores u (coalesced).
+// The next chunk's entries load while the current one is summed.  No row
+// pointer is read.
+constexpr int kERowMax = 64;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict__ x, int step) {
+    __shared__ double wred[kWaves][2];
+    __shared__ T rsum_all[kWaves][256];
+    DevScalars* sc = P.sc;
+    if (MODE == SPMV_LANCZOS && sc->done) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T* rsum = rsum_all[wv];
+    int64_t clo, chi;
+    split_range(P.nqc, xcd_lid() * kWaves + wv, gridDim.x * kWaves, clo, chi);
+    int2 cd = make_int2(0, 0);
+    i32x4_t w = {kQPad, kQPad, kQPad, kQPad};
+    T v[4] = {(T)0, (T)0, (T)0, (T)0};
+    auto load_chunk = [&](int64_t c) {
+        cd = P.qc[c];
+        if (lane < cd.y) {
+            const size_t q = (size_t)c * 64 + lane;
+            w = reinterpret_cast<const i32x4_t*>(P.qw)[q];
+            load_vals4(P.qv + 4 * q, v);
+        } else {
+            w = i32x4_t{kQPad, kQPad, kQPad, kQPad};
+        }
+    };
+    auto term = [&](int wd, T val) { return (wd & kQPad) ? (T)0 : val * x[wd & kQColMask]; };
+    T t[4] = {(T)0, (T)0, (T)0, (T)0};
+    T xr0 = (T)0, sr0 = (T)0;
+    bool s0 = false, s1 = false, s2 = false, s3 = false, e3 = false;
+    int pc = 0, r0 = 0, nq = 0, nrows = 0;
+    // the current chunk's flags and row numbers, and all of its loads
+    auto issue = [&]() {
+        r0 = cd.x;
+        nq = cd.y;
+        const bool valid = lane < nq;
+        s0 = valid && (w.x & kQStart);
+        s1 = valid && (w.y & kQStart);
+        s2 = valid && (w.z & kQStart);
+        s3 = valid && (w.w & kQStart);
+        const unsigned long long b0 = __ballot(s0), b1 = __ballot(s1), b2 = __ballot(s2), b3 = __ballot(s3);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        pc = __popcll(b0 & below) + __popcll(b1 & below) + __popcll(b2 & below) + __popcll(b3 & below);
+        nrows = __popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3);
+        e3 = valid && ((lane == nq - 1) || (lane < 63 && ((b0 >> (lane + 1)) & 1ull)));   // lane ends a row
+        t[0] = term(w.x, v[0]);
+        t[1] = term(w.y, v[1]);
+        t[2] = term(w.z, v[2]);
+        t[3] = term(w.w, v[3]);
+        if (lane < nrows) {
+            xr0 = x[r0 + lane];
+            sr0 = P.s[r0 + lane];
+        }
+    };
+    if (clo < chi) {   // the first chunk's loads are in flight before the scale reduction
+        load_chunk(clo);
+        issue();
+    }
+    double xs;
+    if (!spmv_scale<MODE>(P, step, true, xs)) return;
+    const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t c = clo; c < chi; ++c) {
+        if (c != clo) issue();
+        if (c + 1 < chi) load_chunk(c + 1);
+        const bool valid = lane < nq;
+        // the lane's sum of the row open at its end (from its last start on)
+        T a = t[0];
+        a = s1 ? t[1] : a + t[1];
+        a = s2 ? t[2] : a + t[2];
+        a = s3 ? t[3] : a + t[3];
+        if (!valid) a = (T)0;
+        const int rid = pc + (int)s0 + (int)s1 + (int)s2 + (int)s3 - 1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T ya = __shfl_up(a, off, 64);
+            const int yr = __shfl_up(rid, off, 64);
+            if (lane >= off && yr == rid) a += ya;
+        }
+        T in = __shfl_up(a, 1, 64);   // running sum of the row open at this lane's start
+        if (lane == 0) in = (T)0;
+        if (valid) {
+            int id = pc + (int)s0 - 1;
+            T f = s0 ? t[0] : in + t[0];
+            if (s1) rsum[id] = f;
+            id += (int)s1;
+            f = s1 ? t[1] : f + t[1];
+            if (s2) rsum[id] = f;
+            id += (int)s2;
+            f = s2 ? t[2] : f + t[2];
+            if (s3) rsum[id] = f;
+            id += (int)s3;
+            f = s3 ? t[3] : f + t[3];
+            if (e3) rsum[id] = f;
+        }
+        wave_sync();
+        for (int i = lane; i < nrows; i += 64) {
+            const int64_t r = r0 + i;
+            const double xr = (i == lane) ? (double)xr0 : (double)x[r];
+            const double sr = (i == lane) ? (double)sr0 : (double)P.s[r];
+            const double off = (double)rsum[i];
+            if (MODE == SPMV_LANCZOS) {
+                const T ut = (T)((off + sr * xr) * xs);
+                P.u[r] = ut;
+                acc0 += xr * xs * (double)ut;
+            } else if (MODE == SPMV_OBJ) {
+                const double cvr = (off + P.dC[r] * xr) * xs;
+                const double dvr = (off + sr * xr) * xs;
+                acc0 += xr * xs * cvr;
+                const double rr = dvr - xi * xr * xs;
+                acc1 += rr * rr;
+            } else {
+                P.u[r] = (T)(off + sr * xr);
+            }
+        }
+        wave_sync();
+    }
+    if (MODE == SPMV_APPLY) return;
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    if (lane == 0) {
+        wred[wv][0] = acc0;
+        wred[wv][1] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i < kWaves; ++i) {
+            s0 += wred[i][0];
+            s1 += wred[i][1];
+        }
+        if (MODE == SPMV_LANCZOS) {
+            P.p_spmv[blockIdx.x] = s0;
+        } else {
+            P.p_obj[(size_t)blockIdx.x * 2 + 0] = s0;
+            P.p_obj[(size_t)blockIdx.x * 2 + 1] = s1;
+        }
+    }
+}
+
 // Rows of the workgroup's share in quads: for (qd...) { r = 4 qd; m = rows in quad }.
 #define SCG_FOR_QUADS(n)                                                   \
     int64_t qlo_, qhi_;                                                    \

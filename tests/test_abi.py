@@ -55,7 +55,7 @@ def test_workspace_size_and_validation():
     assert st2 == _lib.SCG_OK and b2 < b
     bad = [dict(R=0), dict(R=33), dict(n=5, R=6), dict(T=0), dict(beta0=0.0), dict(beta0=-1.0), dict(K=-1.0),
            dict(q_mode=2), dict(q_mode=1, q_fixed=0), dict(reorth=3), dict(reorth=-1), dict(precision=7), dict(n=0),
-           dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_lanes=1, segments=2), dict(spmv_lanes=1, matrix_format=1), dict(spmv_grid=-1), dict(spmv_grid=4096),
+           dict(spmv_lanes=3), dict(spmv_lanes=64), dict(spmv_lanes=1, segments=2), dict(spmv_grid=-1), dict(spmv_grid=4096),
            dict(q_mode=1, q_fixed=600, n=10_000), dict(basis_mode=2), dict(basis_mode=-1), dict(omega_mode=2),
            dict(basis_mode=1, reorth=2), dict(trace_mode=2), dict(trace_mode=-1), dict(constraint_set=3), dict(constraint_set=-1),
                dict(batch_kernel=1)]
@@ -91,10 +91,14 @@ def test_storage_optimal_modes_shrink_the_workspace():
     assert abs((c4 - c3) - (b4 - d3)) <= slack
 
 
-def test_quad_chunk_layout_reservation():
-    # column words for chunks of 64 quads, each row padded to whole quads: at
-    # most nnz/4 + n quads, every chunk but the last holding at least 33 of
-    # them; not reserved when a row-block product or stored values are forced
+def test_chunk_layout_reservation():
+    # the quad-chunk layout: column words for chunks of 64 quads, each row
+    # padded to whole quads: at most nnz/4 + n quads, every chunk but the last
+    # holding at least 33 of them; the entry-chunk layout (stored values):
+    # chunks of 256 entries, a row taking max(1, d) <= 64 of them, every chunk
+    # but the last holding at least 193: words for the larger count, values
+    # (FP64 here) for the entry layout only, which stored values force; neither
+    # when a row-block product is forced
     n, nnz = 1_000_000, 9_000_000
     st0, b_auto = _ws(n=n, nnz=nnz)
     st1, b_rows = _ws(n=n, nnz=nnz, spmv_lanes=2)
@@ -102,8 +106,10 @@ def test_quad_chunk_layout_reservation():
     st3, b_quad = _ws(n=n, nnz=nnz, spmv_lanes=1)
     assert st0 == st1 == st2 == st3 == _lib.SCG_OK
     chunks = (nnz // 4 + n + 1) // 33 + 2
-    assert b_rows == b_vals
-    assert 0 <= (b_auto - b_rows) - (256 * 4 * chunks + 8 * chunks) <= 2 * 256
+    echunks = (nnz + n) // 193 + 2
+    assert chunks > echunks
+    assert 0 <= (b_auto - b_rows) - (256 * 4 * chunks + 8 * 256 * echunks + 8 * chunks) <= 3 * 256
+    assert 0 <= (b_vals - b_rows) - (256 * 4 * echunks + 8 * 256 * echunks + 8 * echunks) <= 3 * 256
     # the forced quad-chunk product never splits columns: no room for eight segments'
     # row pointers, row-block descriptors and concurrent partial sums (FP64, ld = n here)
     seg = 7 * 4 * (n + 1) + 7 * 8 * (n + 2) + 8 * 8 * n
