@@ -874,10 +874,11 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
     // the kernel's occupancy keeps resident
     if (c->nqc > 0 && (c->prm.spmv_lanes == 0 || c->prm.spmv_lanes == 1) && c->prm.segments <= 1) {
         const int g_keep = c->Gs;
-        const int g_res = chunk_resident_grid<T>(c);
-        for (int g : {1536, 2048, g_res}) {
+        const int cand[3] = {1536, 2048, chunk_resident_grid<T>(c)};
+        for (int i = 0; i < 3; ++i) {
+            const int g = cand[i];
             if (c->prm.spmv_grid > 0 && g != 1536) continue;   // a forced grid is applied afterwards
-            if (g == g_res && (g == 1536 || g == 2048 || g < 8)) continue;
+            if (i == 2 && (g == 1536 || g == 2048 || g < 8)) continue;   // the resident grid, if another
             c->Gs = g;
             float ms = 0.f;
             HIP_TRY(time_lanes(1, ms));

@@ -529,6 +529,20 @@ __global__ __launch_bounds__(kBlock) void k_xcombine(Prob<T> P, const T* __restr
     }
 }
 
+// The chunks a wave takes in the chunk products: the XCD that dispatches the
+// workgroup owns one contiguous eighth of the chunks, and its waves take them
+// round-robin (chunk lo, lo + step, ...), so at any moment they work on
+// neighbouring rows and the x entries those rows gather stay in the XCD's L2
+// (each wave taking a contiguous range instead spreads them over the whole
+// eighth).  The grid is a multiple of the XCD count.
+__device__ __forceinline__ void chunk_sweep(int64_t nchunks, int wv, int64_t& lo, int64_t& hi, int64_t& step) {
+    int64_t xlo, xhi;
+    split_range(nchunks, blockIdx.x % kXcd, kXcd, xlo, xhi);
+    lo = xlo + (int64_t)(blockIdx.x / kXcd) * kWaves + wv;
+    hi = xhi;
+    step = (int64_t)(gridDim.x / kXcd) * kWaves;
+}
+
 // The same product over the quad-chunk layout (matrices whose off-diagonal
 // values share one magnitude and whose rows hold at most kQRowMax entries).
 // Each row's column words are padded to whole 16-byte quads and rows are
@@ -539,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_xcombine(Prob<T> P, const T* __restr
 // before it (ballot), rows are summed by a segmented scan across the lanes,
 // and the row's last lane applies the shift and the scale exactly as k_spmv
 // does.  There is no LDS staging and no row-pointer stream, and every lane's
-// gathers depend on one load only.
+// gathers depend on one load only.  A wave's chunks follow chunk_sweep.
 constexpr int kQStart = 1 << 30, kQPad = 1 << 29, kQColMask = (1 << 29) - 1;
 constexpr int kQRowMax = 128;   // off-diagonal entries of the longest row the layout takes
 
@@ -555,8 +569,8 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
     DevScalars* sc = P.sc;
     if (MODE == SPMV_LANCZOS && sc->done) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t clo, chi;
-    split_range(P.nqc, xcd_lid() * kWaves + wv, gridDim.x * kWaves, clo, chi);
+    int64_t clo, chi, cstep;
+    chunk_sweep(P.nqc, wv, clo, chi, cstep);
     int2 cd = make_int2(0, 0);
     i32x4_t w = {kQPad, kQPad, kQPad, kQPad};
     T tf[4] = {(T)0, (T)0, (T)0, (T)0};
@@ -573,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
     const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
     const double cv = P.cval;
     double acc0 = 0.0, acc1 = 0.0;
-    for (int64_t c = clo; c < chi; ++c) {
+    for (int64_t c = clo; c < chi; c += cstep) {
         const bool valid = lane < cd.y;
         const bool start = valid && (w.x & kQStart);
         const unsigned long long bal = __ballot(start);
@@ -584,9 +598,9 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
                              (quad_term<T, FMT>(x, w.z) + quad_term<T, FMT>(x, w.w))
                        : (T)0;
         const int r0 = cd.x, nq = cd.y;
-        if (c + 1 < chi) {
-            cd = P.qc[c + 1];
-            w = (lane < cd.y) ? reinterpret_cast<const i32x4_t*>(P.qw)[(size_t)(c + 1) * 64 + lane]
+        if (c + cstep < chi) {
+            cd = P.qc[c + cstep];
+            w = (lane < cd.y) ? reinterpret_cast<const i32x4_t*>(P.qw)[(size_t)(c + cstep) * 64 + lane]
                               : i32x4_t{kQPad, kQPad, kQPad, kQPad};
         }
 #pragma unroll
@@ -656,8 +670,8 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
 //     LDS slice;
 //   - one lane per row applies the shift and the scale exactly as k_spmv does
 //     and stores u (coalesced).
-// The next chunk's entries load while the current one is summed.  No row
-// pointer is read.
+// The next chunk's entries load while the current one is summed; a wave's
+// chunks follow chunk_sweep.  No row pointer is read.
 constexpr int kERowMax = 64;
 
 template <typename T, int MODE>
@@ -668,8 +682,9 @@ __global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict
     if (MODE == SPMV_LANCZOS && sc->done) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     T* rsum = rsum_all[wv];
-    int64_t clo, chi;
-    split_range(P.nqc, xcd_lid() * kWaves + wv, gridDim.x * kWaves, clo, chi);
+    // the chunks of the dispatching XCD's eighth, round-robin over its waves
+    int64_t clo, chi, cstep;
+    chunk_sweep(P.nqc, wv, clo, chi, cstep);
     int2 cd = make_int2(0, 0);
     i32x4_t w = {kQPad, kQPad, kQPad, kQPad};
     T v[4] = {(T)0, (T)0, (T)0, (T)0};
@@ -719,9 +734,9 @@ __global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict
     if (!spmv_scale<MODE>(P, step, true, xs)) return;
     const double xi = (MODE == SPMV_OBJ) ? sc->xi : 0.0;
     double acc0 = 0.0, acc1 = 0.0;
-    for (int64_t c = clo; c < chi; ++c) {
+    for (int64_t c = clo; c < chi; c += cstep) {
         if (c != clo) issue();
-        if (c + 1 < chi) load_chunk(c + 1);
+        if (c + cstep < chi) load_chunk(c + cstep);
         const bool valid = lane < nq;
         // the lane's sum of the row open at its end (from its last start on)
         T a = t[0];

@@ -82,7 +82,8 @@ def test_operator_at_full_size_within_rounding_bound(k, precision):
 # stored), the row-block product with one or four sequential column segments,
 # and the eight concurrent segments (power law)
 FORCED = [(2, dict(spmv_lanes=1, spmv_grid=2048)), (2, dict(spmv_lanes=2, segments=1)),
-          (5, dict(spmv_lanes=1, spmv_grid=1536)), (5, dict(spmv_lanes=1, spmv_grid=2048)),
+          (5, dict(spmv_lanes=1, spmv_grid=1536)), (5, dict(spmv_lanes=1, spmv_grid=1792)),
+          (5, dict(spmv_lanes=1, spmv_grid=2048)),
           (5, dict(spmv_lanes=2, segments=1, spmv_grid=1024)), (5, dict(spmv_lanes=2, segments=8, spmv_grid=1024)),
           (3, dict(spmv_lanes=2, segments=8, spmv_grid=1024)), (3, dict(spmv_lanes=4, segments=4, spmv_grid=1536))]
 
