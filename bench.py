@@ -55,7 +55,7 @@ HBM_PEAK_GBS = 8000.0
 # sums + k_xcombine)
 PROBE_SHAPES = {
     2: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((2, 1536, 2), (2, 0, 2), (1, 1536, 1), (1, 2048, 1)),
-    3: ((2, 1024, 8), (2, 2048, 8), (4, 1536, 4), (4, 0, 1)),
+    3: ((2, 1024, 8), (2, 2048, 8), (4, 1536, 4), (4, 0, 1), (1, 1024, 8), (1, 2048, 8)),
     5: tuple((l, g, 1) for l in (2, 4) for g in (1024, 1536, 0)) + ((1, 1536, 1), (1, 1792, 1), (1, 2048, 1)),
 }
 TRAFFIC_FILES = {
@@ -88,6 +88,8 @@ def spmv_kernel_name(summ: dict) -> str:
     """The product kernel the autotuner chose: lanes 1 is a chunk layout (quad chunks of column words, or
     entry chunks when values are stored); with 8 column segments the row-block kernel runs them in one launch
     and k_xcombine adds the segment sums."""
+    if summ["spmv_lanes"] == 1 and summ["spmv_segments"] == 8:
+        return "k_spmvx + k_spmvx_long + k_xcombine"
     if summ["spmv_lanes"] == 1:
         return "k_spmve" if summ["matrix_format"] == 0 else "k_spmvq"
     return "k_spmv + k_xcombine" if summ["spmv_segments"] == 8 else "k_spmv"

@@ -101,8 +101,11 @@ typedef struct {
                                padded to 16-byte quads, rows of at most 128 off-diagonal
                                entries); with stored values the entry-chunk layout (column
                                words and values unpadded, a row starting anywhere in a quad,
-                               rows of at most 64 off-diagonal entries); one column segment;
-                               init returns SCG_EINVAL when the matrix does not qualify      */
+                               rows of at most 64 off-diagonal entries); one column segment,
+                               or eight (segments = 8: each column slice's row segments in
+                               entry chunks, segments of more than 64 entries summed by a
+                               wave of their own, any matrix); init returns SCG_EINVAL when
+                               the matrix does not qualify                                    */
     int32_t  spmv_grid;     /* SpMV workgroups: 0 = autotuned / one row-block range per wave,
                                or a cap (rounded to a multiple of 8, at most 2048)            */
     int32_t  basis_mode;    /* Lanczos basis storage: 0 = all q+1 vectors kept (ld x (q+1)),
@@ -165,7 +168,8 @@ typedef struct {
     double infeasibility;     /* ||diag X - b|| (box or ball: dist_K)       */
     double p_scaled, tau_scaled, c_F, alpha, alpha_scaled;
     int32_t spmv_lanes;       /* lanes per row chosen for the SpMV row reduction (1: a chunk
-                                 product, quad-chunk or entry-chunk by matrix_format)          */
+                                 product: quad-chunk or entry-chunk by matrix_format, or with
+                                 spmv_segments = 8 the column slices in entry chunks)          */
     int32_t spmv_segments;    /* column segments of the SpMV (8: the concurrent form)          */
     int32_t matrix_format;    /* storage of the off-diagonal values: 0 values, 1 columns only
                                  (common value), 2 columns with sign bit (common magnitude)  */

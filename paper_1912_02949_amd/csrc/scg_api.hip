@@ -76,9 +76,20 @@ int seg_cap(const scg_params& p, int64_t n, int64_t nnz) {
     return 1;
 }
 
+// Chunks of the sliced entry-chunk layout (the eight concurrent column segments
+// over entry chunks; 0: never used with these parameters).  Slice s holds
+// max(1, d) entries per row for its d <= kERowMax entries of the row, else one
+// (the long segment is stored apart); every chunk of a slice but its last holds
+// at least 256 - kERowMax + 1 entries, and the slices hold at most nnz + 8 n.
+int64_t xchunk_cap(const scg_params& p, int64_t n, int64_t nnz) {
+    if (seg_cap(p, n, nnz) < kSegMax || (p.segments != 0 && p.segments != kSegMax)) return 0;
+    if ((p.spmv_lanes != 0 && p.spmv_lanes != 1) || n >= ((int64_t)1 << 29)) return 0;
+    return (nnz + kSegMax * n) / (256 - kERowMax + 1) + 2 * kSegMax;
+}
+
 struct Layout {
     size_t rp, col, val, dC, b, z, y, s, V, u, v, xp, Om, S, rb, sc, part, counter, logs, recon, racc, lo, hi, qw, qv,
-        qc, total;
+        qc, xqw, xqv, xqc, xlseg, xlw, xlv, total;
     size_t recon_bytes;
 };
 
@@ -122,6 +133,13 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.qw = take(sizeof(int32_t) * 256 * (size_t)std::max(nqc, nec));
     L.qv = take(es * 256 * (size_t)nec);
     L.qc = take(sizeof(int2) * (size_t)std::max(nqc, nec));
+    const int64_t nxc = xchunk_cap(p, n, nnz);
+    L.xqw = take(sizeof(int32_t) * 256 * (size_t)nxc);
+    L.xqv = take(es * 256 * (size_t)nxc);
+    L.xqc = take(sizeof(int2) * (size_t)nxc);
+    L.xlseg = take(nxc > 0 ? sizeof(int4) * (size_t)(nnz / (kERowMax + 1) + kSegMax) : 0);
+    L.xlw = take(nxc > 0 ? sizeof(int32_t) * (size_t)nnz : 0);
+    L.xlv = take(nxc > 0 ? es * (size_t)nnz : 0);
     L.total = off;
     return L;
 }
@@ -231,9 +249,47 @@ void launch_spmv_f(scg_ctx* c, const T* x, int step, int lanes) {
     }
 }
 
+// The eight concurrent column segments over entry chunks: the slice pass, the
+// long segments, and the combining pass.
+template <typename T, int MODE>
+void launch_spmv_xc(scg_ctx* c, const T* x, int step) {
+    const Prob<T> P = prob<T>(c);
+    XcArgs a{};
+    a.qw = c->xqw;
+    a.qv = c->xqv;
+    a.qc = c->xqc;
+    a.lseg = c->xlseg;
+    a.lw = c->xlw;
+    a.lv = c->xlv;
+    for (int s = 0; s <= kSegMax; ++s) {
+        a.cb[s] = c->xcb[s];
+        a.lb[s] = c->xlb[s];
+    }
+    a.xpart = c->xpart;
+    a.xld = c->ld;
+    a.lanczos = (MODE == SPMV_LANCZOS) ? 1 : 0;
+    const dim3 g(c->Gs), b(kBlock);
+    const bool lng = c->xlb[kSegMax] > 0;
+    if (c->fmt == FMT_PAT) {
+        hipLaunchKernelGGL((k_spmvx<T, FMT_PAT>), g, b, 0, c->stream, P, x, a);
+        if (lng) hipLaunchKernelGGL((k_spmvx_long<T, FMT_PAT>), g, b, 0, c->stream, P, x, a);
+    } else if (c->fmt == FMT_SGN) {
+        hipLaunchKernelGGL((k_spmvx<T, FMT_SGN>), g, b, 0, c->stream, P, x, a);
+        if (lng) hipLaunchKernelGGL((k_spmvx_long<T, FMT_SGN>), g, b, 0, c->stream, P, x, a);
+    } else {
+        hipLaunchKernelGGL((k_spmvx<T, FMT_VAL>), g, b, 0, c->stream, P, x, a);
+        if (lng) hipLaunchKernelGGL((k_spmvx_long<T, FMT_VAL>), g, b, 0, c->stream, P, x, a);
+    }
+    hipLaunchKernelGGL((k_xcombine<T, MODE>), g, b, 0, c->stream, P, x, step, (const T*)c->xpart, (int64_t)c->ld);
+}
+
 template <typename T, int MODE>
 void launch_spmv(scg_ctx* c, const T* x, int step, int lanes = 0) {
     if (lanes == 0) lanes = c->lanes;
+    if (lanes == 1 && c->xseg) {   // the concurrent column segments over entry chunks
+        launch_spmv_xc<T, MODE>(c, x, step);
+        return;
+    }
     if (lanes == 1) {   // the chunk products: padded column-word quads, or entries with values
         const dim3 g(c->Gs), b(kBlock);
         if (c->fmt == FMT_PAT) hipLaunchKernelGGL((k_spmvq<T, MODE, FMT_PAT>), g, b, 0, c->stream, prob<T>(c), x, step);
@@ -598,6 +654,102 @@ __global__ __launch_bounds__(kBlock) void k_scatter_seg(int64_t n, const int64_t
 }
 
 // Build the nseg-segment layout of the off-diagonal part from the input CSR.
+// The sliced entry-chunk layout from the sliced CSR that build_segments has just
+// written (row pointers of slice s at rp + s (n + 1), entries in col / val):
+// thread per (slice, row); eoff = the segment's first slot.  The words and
+// values of every chunk were filled with padding (kQPad, 0) beforehand.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_xchunks(int64_t n, const int32_t* rp, const int32_t* col,
+                                                            const T* val, const int32_t* eoff, int32_t* qw, T* qv,
+                                                            int fmt) {
+    const int64_t tot = (int64_t)kSegMax * n;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < tot; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t s = i / n, r = i - s * n;
+        const int32_t* rps = rp + s * (n + 1);
+        const int32_t e0 = rps[r], d = rps[r + 1] - e0;
+        const int64_t o = eoff[i];
+        if (d == 0 || d > kERowMax) {
+            qw[o] = kQPad | kQStart;
+            continue;
+        }
+        for (int k = 0; k < d; ++k) {
+            qw[o + k] = (k == 0) ? (col[e0 + k] | kQStart) : col[e0 + k];
+            if (fmt == FMT_VAL) qv[o + k] = val[e0 + k];
+        }
+    }
+}
+
+// Entries of the long segments, one wave per segment: (row, first entry, entries, source entry).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_long(int64_t nl, const int4* lseg, const int32_t* col, const T* val,
+                                                      int32_t* lw, T* lv, int fmt) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t k = (int64_t)blockIdx.x * kWaves + wv; k < nl; k += (int64_t)gridDim.x * kWaves) {
+        const int4 d = lseg[k];
+        const int64_t src = d.w;
+        for (int e = lane; e < d.z; e += 64) {
+            lw[(int64_t)d.y + e] = col[src + e];
+            if (fmt == FMT_VAL) lv[(int64_t)d.y + e] = val[src + e];
+        }
+    }
+}
+
+template <typename T>
+scg_status build_xchunks(scg_ctx* c, const std::vector<int32_t>& hc, const std::vector<int32_t>& hrp) {
+    c->nxc = 0;
+    if (!c->xqw) return SCG_OK;
+    const int64_t n = c->n;
+    std::vector<int32_t> eoff((size_t)kSegMax * n);
+    std::vector<int2> qc;
+    std::vector<int4> lseg;
+    int64_t loff = 0;
+    for (int s = 0; s < kSegMax; ++s) {
+        c->xcb[s] = (int64_t)qc.size();
+        c->xlb[s] = (int64_t)lseg.size();
+        int fill = 256;
+        for (int64_t r = 0; r < n; ++r) {
+            const int d = hc[(size_t)s * n + r];
+            const int slots = (d == 0 || d > kERowMax) ? 1 : d;
+            if (fill + slots > 256) {
+                qc.push_back(make_int2((int)r, 0));
+                fill = 0;
+            }
+            const int64_t o = (int64_t)(qc.size() - 1) * 256 + fill;
+            if (o > INT32_MAX) return SCG_OK;
+            eoff[(size_t)s * n + r] = (int32_t)o;
+            fill += slots;
+            qc.back().y = (fill + 3) / 4;
+            if (d > kERowMax) {
+                lseg.push_back(make_int4((int)r, (int)loff, d, hrp[(size_t)s * (n + 1) + r]));
+                loff += d;
+            }
+        }
+    }
+    c->xcb[kSegMax] = (int64_t)qc.size();
+    c->xlb[kSegMax] = (int64_t)lseg.size();
+    if ((int64_t)qc.size() > c->xqc_cap || (int64_t)lseg.size() > c->xlseg_cap || loff > c->nnz_in)
+        return SCG_OK;   // cannot happen within the reserved bounds
+    // the offsets go through the concurrent-segment partials (8 ld elements of at least 4 bytes), unused yet
+    int32_t* deoff = static_cast<int32_t*>(c->xpart);
+    const size_t slots = 256 * qc.size();
+    HIP_TRY(hipMemcpyAsync(deoff, eoff.data(), sizeof(int32_t) * eoff.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->xqc, qc.data(), sizeof(int2) * qc.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)c->xqw, kQPad, slots, c->stream));
+    HIP_TRY(hipMemsetAsync(c->xqv, 0, sizeof(T) * slots, c->stream));
+    hipLaunchKernelGGL((k_scatter_xchunks<T>), dim3(c->G), dim3(kBlock), 0, c->stream, n, c->rp, c->col,
+                       (const T*)c->val, deoff, c->xqw, (T*)c->xqv, c->fmt);
+    HIP_TRY(hipGetLastError());
+    if (!lseg.empty()) {
+        HIP_TRY(hipMemcpyAsync(c->xlseg, lseg.data(), sizeof(int4) * lseg.size(), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL((k_copy_long<T>), dim3(c->G), dim3(kBlock), 0, c->stream, (int64_t)lseg.size(), c->xlseg,
+                           c->col, (const T*)c->val, c->xlw, (T*)c->xlv, c->fmt);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->nxc = (int64_t)qc.size();
+    return SCG_OK;
+}
+
 template <typename T>
 scg_status build_segments(scg_ctx* c, int nseg, const int64_t* row_ptr, const int32_t* col, const double* val) {
     const int64_t n = c->n;
@@ -641,6 +793,7 @@ scg_status build_segments(scg_ctx* c, int nseg, const int64_t* row_ptr, const in
                        c->rp, (int64_t)(n + 1), c->col, (T*)c->val, 1.0 / c->c_F, c->fmt);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (nseg == kSegMax && c->nxc == 0) return build_xchunks<T>(c, hc, hrp);   // the layout depends on the slices only
     return SCG_OK;
 }
 
@@ -870,9 +1023,31 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         c->xseg = false;
         c->Gs = g_keep;
     }
+    // the eight concurrent segments over entry chunks (the layout is built with the eight segments)
+    if (c->xqw && c->xpart && (c->prm.spmv_lanes == 0 || c->prm.spmv_lanes == 1) &&
+        (c->prm.segments == kSegMax || (c->prm.segments == 0 && c->n >= (1 << 18)))) {
+        if (c->nxc == 0) {
+            scg_status st = build_segments<T>(c, kSegMax, row_ptr, col, val);
+            if (st != SCG_OK) return st;
+        }
+        if (c->nxc > 0) {
+            const int g_keep = c->Gs;
+            c->xseg = true;
+            for (int g : {2048, 1024}) {
+                if (c->prm.spmv_grid > 0 && g != 2048) continue;   // a forced grid is applied afterwards
+                c->Gs = g;
+                float ms = 0.f;
+                HIP_TRY(time_lanes(1, ms));
+                if (better(ms)) { best = ms; best_l = 1; best_s = kSegMax; best_g = g; best_x = true; }
+            }
+            c->xseg = false;
+            c->Gs = g_keep;
+        }
+    }
     // the chunk product, when the matrix has a chunk layout: 1536 or 2048 workgroups, or as many as
     // the kernel's occupancy keeps resident
     if (c->nqc > 0 && (c->prm.spmv_lanes == 0 || c->prm.spmv_lanes == 1) && c->prm.segments <= 1) {
+        c->xseg = false;
         const int g_keep = c->Gs;
         const int cand[3] = {1536, 2048, chunk_resident_grid<T>(c)};
         for (int i = 0; i < 3; ++i) {
@@ -1015,7 +1190,7 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
         }
     }
     // forced SpMV shape (overrides the autotuner); the quad-chunk product needs its layout
-    if (c->prm.spmv_lanes == 1 && c->nqc == 0) return SCG_EINVAL;
+    if (c->prm.spmv_lanes == 1 && (c->xseg ? c->nxc == 0 : c->nqc == 0)) return SCG_EINVAL;
     if (c->prm.spmv_lanes > 0) c->lanes = c->prm.spmv_lanes;
     if (c->prm.spmv_grid > 0) c->Gs = std::min(c->Gs, std::max(8, round8(c->prm.spmv_grid)));
     HIP_TRY(hipMemsetAsync(c->logs, 0, sizeof(scg_iter_log) * c->prm.T, c->stream));
@@ -1081,7 +1256,7 @@ bool params_ok(const scg_params* p, int64_t n, int64_t nnz) {
     if (qmax_for(*p, n) + 1 > kQCap) return false;
     const int l = p->spmv_lanes;
     if (l != 0 && l != 1 && l != 2 && l != 4 && l != 8 && l != 16 && l != 32) return false;
-    if (l == 1 && p->segments > 1) return false;   // the chunk products
+    if (l == 1 && p->segments > 1 && p->segments != kSegMax) return false;   // the chunk products
     if (p->segments != 0 && p->segments != 1 && p->segments != 2 && p->segments != 4 && p->segments != kSegMax)
         return false;
     if (p->spmv_grid < 0 || p->spmv_grid > kGMax) return false;
@@ -1185,6 +1360,16 @@ scg_status sketchycgal_init(scg_ctx** out, const scg_params* p, int64_t n, int64
     c->qv = (nec > 0) ? (void*)(base + L.qv) : nullptr;
     c->qc = (c->qc_cap > 0) ? (int2*)(base + L.qc) : nullptr;
     c->nqc = 0;
+    c->xqc_cap = xchunk_cap(*p, n, nnz);
+    c->xqw = (c->xqc_cap > 0) ? (int32_t*)(base + L.xqw) : nullptr;
+    c->xqv = (c->xqc_cap > 0) ? (void*)(base + L.xqv) : nullptr;
+    c->xqc = (c->xqc_cap > 0) ? (int2*)(base + L.xqc) : nullptr;
+    c->xlseg = (c->xqc_cap > 0) ? (int4*)(base + L.xlseg) : nullptr;
+    c->xlseg_cap = (c->xqc_cap > 0) ? nnz / (kERowMax + 1) + kSegMax : 0;
+    c->xlw = (c->xqc_cap > 0) ? (int32_t*)(base + L.xlw) : nullptr;
+    c->xlv = (c->xqc_cap > 0) ? (void*)(base + L.xlv) : nullptr;
+    c->nxc = 0;
+    for (int s = 0; s <= kSegMax; ++s) c->xcb[s] = c->xlb[s] = 0;
     scg_status st = (p->precision == SCG_FP32_STREAM) ? init_typed<float>(c, row_ptr, col, val, b, omega)
                                                        : init_typed<double>(c, row_ptr, col, val, b, omega);
     if (st != SCG_OK) {

@@ -160,6 +160,18 @@ struct scg_ctx {
     int2* qc;        // per chunk: (first row, quads used)
     int64_t nqc;     // chunks built (0: the matrix does not qualify)
     int64_t qc_cap;  // chunks reserved
+    // the sliced entry-chunk layout of the concurrent column segments (spmv_lanes 1, segments 8)
+    int32_t* xqw;    // column words, 256 per chunk (null when not reserved)
+    void* xqv;       // values beside them
+    int2* xqc;       // per chunk: (first row, quads used)
+    int64_t xqc_cap; // chunks reserved
+    int64_t nxc;     // chunks built (0: not built)
+    int64_t xcb[scg::kSegMax + 1];   // chunks of slice s: [xcb[s], xcb[s + 1])
+    int4* xlseg;     // long segments: (row, first entry, entries, unused)
+    int64_t xlseg_cap;
+    int32_t* xlw;    // their column words (at most nnz)
+    void* xlv;       // and values
+    int64_t xlb[scg::kSegMax + 1];   // long segments of slice s: [xlb[s], xlb[s + 1])
     std::map<int, hipGraphExec_t> graphs;   // one captured iteration per Lanczos step count q (non-null stream)
 };
 

@@ -812,6 +812,134 @@ __global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict
     }
 }
 
+// The concurrent column segments over entry chunks (spmv_lanes = 1 with eight
+// segments).  The columns are cut into kSegMax slices; for each slice the
+// entries of every row that fall in it (its segment) are packed into chunks of
+// 256 entries as in the entry-chunk layout, rows in order and whole, a segment
+// with no entry or with more than kERowMax entries holding one padding entry.
+// Workgroup b works on slice b mod 8, the XCD that dispatches it, so each XCD's
+// L2 only holds its own eighth of x; the XCD's waves take its chunks
+// round-robin and store each row's raw slice sum in xpart[slice * xld + r].
+// The long segments (more than kERowMax entries, stored apart) are summed by
+// k_spmvx_long after this pass, one wave per segment, which overwrites the
+// placeholder's zero; k_xcombine then adds the eight partials of each row.
+struct XcArgs {
+    const int32_t* qw;   // column words, 256 per chunk, flags as in the entry-chunk layout
+    const void* qv;      // values beside the words (values stored), else null
+    const int2* qc;      // per chunk: (first row, quads used)
+    int64_t cb[kSegMax + 1];   // chunks of slice s: [cb[s], cb[s + 1])
+    const int4* lseg;    // long segments: (row, first entry, entries, unused)
+    int64_t lb[kSegMax + 1];   // long segments of slice s: [lb[s], lb[s + 1])
+    const int32_t* lw;   // their column words
+    const void* lv;      // and values (values stored), else null
+    void* xpart;
+    int64_t xld;
+    int lanczos;
+};
+
+template <typename T, int FMT>
+__device__ __forceinline__ T xc_term(const T* __restrict__ x, int w, T v) {
+    if (w & kQPad) return (T)0;
+    const T xv = x[w & kQColMask];
+    if (FMT == FMT_VAL) return v * xv;
+    if (FMT == FMT_SGN && w < 0) return -xv;
+    return xv;
+}
+
+template <typename T, int FMT>
+__global__ __launch_bounds__(kBlock) void k_spmvx(Prob<T> P, const T* __restrict__ x, XcArgs a) {
+    __shared__ T rsum_all[kWaves][256];
+    if (a.lanczos && P.sc->done) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T* rsum = rsum_all[wv];
+    const int seg = blockIdx.x % kXcd;
+    const int64_t cstep = (int64_t)(gridDim.x / kXcd) * kWaves;
+    const int64_t clo = a.cb[seg] + (int64_t)(blockIdx.x / kXcd) * kWaves + wv, chi = a.cb[seg + 1];
+    T* out = static_cast<T*>(a.xpart) + (size_t)seg * a.xld;
+    const T* qv = static_cast<const T*>(a.qv);
+    int2 cd = make_int2(0, 0);
+    i32x4_t w = {kQPad, kQPad, kQPad, kQPad};
+    T v[4] = {(T)0, (T)0, (T)0, (T)0};
+    auto load_chunk = [&](int64_t c) {
+        cd = a.qc[c];
+        if (lane < cd.y) {
+            const size_t q = (size_t)c * 64 + lane;
+            w = reinterpret_cast<const i32x4_t*>(a.qw)[q];
+            if (FMT == FMT_VAL) load_vals4(qv + 4 * q, v);
+        } else {
+            w = i32x4_t{kQPad, kQPad, kQPad, kQPad};
+        }
+    };
+    if (clo < chi) load_chunk(clo);
+    for (int64_t c = clo; c < chi; c += cstep) {
+        const int r0 = cd.x, nq = cd.y;
+        const bool valid = lane < nq;
+        const bool s0 = valid && (w.x & kQStart), s1 = valid && (w.y & kQStart);
+        const bool s2 = valid && (w.z & kQStart), s3 = valid && (w.w & kQStart);
+        const unsigned long long b0 = __ballot(s0), b1 = __ballot(s1), b2 = __ballot(s2), b3 = __ballot(s3);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const int pc = __popcll(b0 & below) + __popcll(b1 & below) + __popcll(b2 & below) + __popcll(b3 & below);
+        const int nrows = __popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3);
+        const bool e3 = valid && ((lane == nq - 1) || (lane < 63 && ((b0 >> (lane + 1)) & 1ull)));
+        const T t0 = xc_term<T, FMT>(x, w.x, v[0]), t1 = xc_term<T, FMT>(x, w.y, v[1]);
+        const T t2 = xc_term<T, FMT>(x, w.z, v[2]), t3 = xc_term<T, FMT>(x, w.w, v[3]);
+        if (c + cstep < chi) load_chunk(c + cstep);
+        T s = t0;
+        s = s1 ? t1 : s + t1;
+        s = s2 ? t2 : s + t2;
+        s = s3 ? t3 : s + t3;
+        if (!valid) s = (T)0;
+        const int rid = pc + (int)s0 + (int)s1 + (int)s2 + (int)s3 - 1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T ya = __shfl_up(s, off, 64);
+            const int yr = __shfl_up(rid, off, 64);
+            if (lane >= off && yr == rid) s += ya;
+        }
+        T in = __shfl_up(s, 1, 64);
+        if (lane == 0) in = (T)0;
+        if (valid) {
+            int id = pc + (int)s0 - 1;
+            T f = s0 ? t0 : in + t0;
+            if (s1) rsum[id] = f;
+            id += (int)s1;
+            f = s1 ? t1 : f + t1;
+            if (s2) rsum[id] = f;
+            id += (int)s2;
+            f = s2 ? t2 : f + t2;
+            if (s3) rsum[id] = f;
+            id += (int)s3;
+            f = s3 ? t3 : f + t3;
+            if (e3) rsum[id] = f;
+        }
+        wave_sync();
+        for (int i = lane; i < nrows; i += 64) out[r0 + i] = rsum[i];
+        wave_sync();
+    }
+}
+
+// The long segments of the sliced chunk layout: one wave per segment, lanes
+// strided over its entries, the sum stored over the placeholder's zero.
+template <typename T, int FMT>
+__global__ __launch_bounds__(kBlock) void k_spmvx_long(Prob<T> P, const T* __restrict__ x, XcArgs a) {
+    if (a.lanczos && P.sc->done) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int seg = blockIdx.x % kXcd;
+    const int64_t kstep = (int64_t)(gridDim.x / kXcd) * kWaves;
+    T* out = static_cast<T*>(a.xpart) + (size_t)seg * a.xld;
+    const T* lv = static_cast<const T*>(a.lv);
+    for (int64_t k = a.lb[seg] + (int64_t)(blockIdx.x / kXcd) * kWaves + wv; k < a.lb[seg + 1]; k += kstep) {
+        const int4 d = a.lseg[k];
+        T acc = (T)0;
+        for (int e = lane; e < d.z; e += 64) {
+            const int64_t i = (int64_t)d.y + e;
+            acc += xc_term<T, FMT>(x, a.lw[i], (FMT == FMT_VAL) ? lv[i] : (T)0);
+        }
+        const double tot = wave_sum((double)acc);
+        if (lane == 0) out[d.x] = (T)tot;
+    }
+}
+
 // Rows of the workgroup's share in quads: for (qd...) { r = 4 qd; m = rows in quad }.
 #define SCG_FOR_QUADS(n)                                                   \
     int64_t qlo_, qhi_;                                                    \

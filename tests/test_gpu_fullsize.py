@@ -80,12 +80,13 @@ def test_operator_at_full_size_within_rounding_bound(k, precision):
 # every product family the autotuner picks between on these workloads, forced:
 # the quad-chunk product (torus), the entry-chunk product (geometric, values
 # stored), the row-block product with one or four sequential column segments,
-# and the eight concurrent segments (power law)
+# and the eight concurrent segments over row blocks or entry chunks (power law)
 FORCED = [(2, dict(spmv_lanes=1, spmv_grid=2048)), (2, dict(spmv_lanes=2, segments=1)),
           (5, dict(spmv_lanes=1, spmv_grid=1536)), (5, dict(spmv_lanes=1, spmv_grid=1792)),
           (5, dict(spmv_lanes=1, spmv_grid=2048)),
           (5, dict(spmv_lanes=2, segments=1, spmv_grid=1024)), (5, dict(spmv_lanes=2, segments=8, spmv_grid=1024)),
-          (3, dict(spmv_lanes=2, segments=8, spmv_grid=1024)), (3, dict(spmv_lanes=4, segments=4, spmv_grid=1536))]
+          (3, dict(spmv_lanes=2, segments=8, spmv_grid=1024)), (3, dict(spmv_lanes=4, segments=4, spmv_grid=1536)),
+          (3, dict(spmv_lanes=1, segments=8, spmv_grid=2048)), (3, dict(spmv_lanes=1, segments=8, spmv_grid=1024))]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])

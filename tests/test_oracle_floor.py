@@ -395,3 +395,28 @@ def test_entry_chunk_trajectory_instances_floor(monkeypatch):
     print("spreads:", spreads)
     assert spreads["mixed"] < 1e-11 and spreads["geometric"] < 1e-11
     assert spreads["er_isolated"] > 1e-10
+
+
+def test_sliced_chunk_instance_two_iteration_floor(monkeypatch):
+    """The power-law instance with stored values of the sliced entry-chunk
+    test (40 000 vertices, hub rows of ~900 entries), two iterations at
+    q = 10: summing every row of every product in reverse order moves the
+    oracle's own p, ||z - b||, v^T C v and z by at most ~3e-12, so the two GPU
+    forms of the eight concurrent segments are held to 5e-11 there."""
+    import oracle.sketchycgal as osc
+    from test_gpu_sliced_chunks import CASES
+    inst = CASES["powerlaw_values"]()
+    prm = OracleParams(R=6, T=2, seed=7, q_mode=1, q_fixed=10)
+    A = sketchy_cgal(inst.to_scipy(), inst.b, prm)
+    orig = osc.scale_problem
+
+    def reversed_scale(C, b, alpha, scale=True):
+        Cs, bs, a, cF = orig(C, b, alpha, scale)
+        return _ReversedRows(Cs), bs, a, cF
+
+    monkeypatch.setattr(osc, "scale_problem", reversed_scale)
+    B = sketchy_cgal(inst.to_scipy(), inst.b, prm)
+    spread = max([np.max(np.abs(A.log[k] - B.log[k])) / np.max(np.abs(A.log[k])) for k in ("p", "infeas", "cv")]
+                 + [np.abs(A.z - B.z).max() / np.abs(A.z).max()])
+    print("spread:", spread)
+    assert 1e-13 < spread < 5e-12
