@@ -695,10 +695,16 @@ __global__ __launch_bounds__(kBlock) void k_copy_long(int64_t nl, const int4* ls
 }
 
 template <typename T>
-scg_status build_xchunks(scg_ctx* c, const std::vector<int32_t>& hc, const std::vector<int32_t>& hrp) {
+scg_status build_xchunks(scg_ctx* c) {
     c->nxc = 0;
-    if (!c->xqw) return SCG_OK;
+    if (!c->xqw || c->nseg != kSegMax) return SCG_OK;
     const int64_t n = c->n;
+    std::vector<int32_t> hrp((size_t)kSegMax * (n + 1)), hc((size_t)kSegMax * n);
+    HIP_TRY(hipMemcpyAsync(hrp.data(), c->rp, sizeof(int32_t) * hrp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int s = 0; s < kSegMax; ++s)
+        for (int64_t r = 0; r < n; ++r)
+            hc[(size_t)s * n + r] = hrp[(size_t)s * (n + 1) + r + 1] - hrp[(size_t)s * (n + 1) + r];
     std::vector<int32_t> eoff((size_t)kSegMax * n);
     std::vector<int2> qc;
     std::vector<int4> lseg;
@@ -793,7 +799,6 @@ scg_status build_segments(scg_ctx* c, int nseg, const int64_t* row_ptr, const in
                        c->rp, (int64_t)(n + 1), c->col, (T*)c->val, 1.0 / c->c_F, c->fmt);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (nseg == kSegMax && c->nxc == 0) return build_xchunks<T>(c, hc, hrp);   // the layout depends on the slices only
     return SCG_OK;
 }
 
@@ -1023,11 +1028,15 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         c->xseg = false;
         c->Gs = g_keep;
     }
-    // the eight concurrent segments over entry chunks (the layout is built with the eight segments)
-    if (c->xqw && c->xpart && (c->prm.spmv_lanes == 0 || c->prm.spmv_lanes == 1) &&
-        (c->prm.segments == kSegMax || (c->prm.segments == 0 && c->n >= (1 << 18)))) {
-        if (c->nxc == 0) {
+    // the eight concurrent segments over entry chunks, when the row-block form of the eight segments
+    // beat every single-launch shape (slicing the columns pays on this matrix) or they are forced
+    if (c->xqw && c->xpart && (best_x || (c->prm.spmv_lanes == 1 && c->prm.segments == kSegMax))) {
+        if (c->nseg != kSegMax) {
             scg_status st = build_segments<T>(c, kSegMax, row_ptr, col, val);
+            if (st != SCG_OK) return st;
+        }
+        if (c->nxc == 0) {
+            scg_status st = build_xchunks<T>(c);
             if (st != SCG_OK) return st;
         }
         if (c->nxc > 0) {
@@ -1187,6 +1196,10 @@ scg_status init_typed(scg_ctx* c, const int64_t* row_ptr, const int32_t* col, co
         if (c->prm.segments == kSegMax) {   // the concurrent form
             c->xseg = true;
             c->Gs = kGMax;
+            if (c->prm.spmv_lanes == 1) {   // over entry chunks
+                st = build_xchunks<T>(c);
+                if (st != SCG_OK) return st;
+            }
         }
     }
     // forced SpMV shape (overrides the autotuner); the quad-chunk product needs its layout
