@@ -138,8 +138,10 @@ Layout make_layout(const scg_params& p, int64_t n, int64_t nnz) {
     L.xqv = take(es * 256 * (size_t)nxc);
     L.xqc = take(sizeof(int2) * (size_t)nxc);
     L.xlseg = take(nxc > 0 ? sizeof(int4) * (size_t)(nnz / (kERowMax + 1) + kSegMax) : 0);
-    L.xlw = take(nxc > 0 ? sizeof(int32_t) * (size_t)nnz : 0);
-    L.xlv = take(nxc > 0 ? es * (size_t)nnz : 0);
+    // long entries: each segment starts on a 16-byte quad, so at most 3 padding words per segment
+    const size_t nlw = (size_t)nnz + 4 * (size_t)(nnz / (kERowMax + 1) + kSegMax);
+    L.xlw = take(nxc > 0 ? sizeof(int32_t) * nlw : 0);
+    L.xlv = take(nxc > 0 ? es * nlw : 0);
     L.total = off;
     return L;
 }
@@ -727,13 +729,14 @@ scg_status build_xchunks(scg_ctx* c) {
             qc.back().y = (fill + 3) / 4;
             if (d > kERowMax) {
                 lseg.push_back(make_int4((int)r, (int)loff, d, hrp[(size_t)s * (n + 1) + r]));
-                loff += d;
+                loff += (d + 3) / 4 * 4;
             }
         }
     }
     c->xcb[kSegMax] = (int64_t)qc.size();
     c->xlb[kSegMax] = (int64_t)lseg.size();
-    if ((int64_t)qc.size() > c->xqc_cap || (int64_t)lseg.size() > c->xlseg_cap || loff > c->nnz_in)
+    if ((int64_t)qc.size() > c->xqc_cap || (int64_t)lseg.size() > c->xlseg_cap ||
+        loff > c->nnz_in + 4 * c->xlseg_cap)
         return SCG_OK;   // cannot happen within the reserved bounds
     // the offsets go through the concurrent-segment partials (8 ld elements of at least 4 bytes), unused yet
     int32_t* deoff = static_cast<int32_t*>(c->xpart);
@@ -747,6 +750,8 @@ scg_status build_xchunks(scg_ctx* c) {
     HIP_TRY(hipGetLastError());
     if (!lseg.empty()) {
         HIP_TRY(hipMemcpyAsync(c->xlseg, lseg.data(), sizeof(int4) * lseg.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)c->xlw, kQPad, (size_t)loff, c->stream));
+        HIP_TRY(hipMemsetAsync(c->xlv, 0, sizeof(T) * (size_t)loff, c->stream));
         hipLaunchKernelGGL((k_copy_long<T>), dim3(c->G), dim3(kBlock), 0, c->stream, (int64_t)lseg.size(), c->xlseg,
                            c->col, (const T*)c->val, c->xlw, (T*)c->xlv, c->fmt);
         HIP_TRY(hipGetLastError());

@@ -918,8 +918,10 @@ __global__ __launch_bounds__(kBlock) void k_spmvx(Prob<T> P, const T* __restrict
     }
 }
 
-// The long segments of the sliced chunk layout: one wave per segment, lanes
-// strided over its entries, the sum stored over the placeholder's zero.
+// The long segments of the sliced chunk layout: one wave per segment, each
+// segment starting on a 16-byte quad (padding words complete its last quad),
+// one quad of four entries per lane at a time; the sum is stored over the
+// placeholder's zero.  The next segment's descriptor loads while one is summed.
 template <typename T, int FMT>
 __global__ __launch_bounds__(kBlock) void k_spmvx_long(Prob<T> P, const T* __restrict__ x, XcArgs a) {
     if (a.lanczos && P.sc->done) return;
@@ -928,15 +930,23 @@ __global__ __launch_bounds__(kBlock) void k_spmvx_long(Prob<T> P, const T* __res
     const int64_t kstep = (int64_t)(gridDim.x / kXcd) * kWaves;
     T* out = static_cast<T*>(a.xpart) + (size_t)seg * a.xld;
     const T* lv = static_cast<const T*>(a.lv);
-    for (int64_t k = a.lb[seg] + (int64_t)(blockIdx.x / kXcd) * kWaves + wv; k < a.lb[seg + 1]; k += kstep) {
-        const int4 d = a.lseg[k];
+    const int64_t k0 = a.lb[seg] + (int64_t)(blockIdx.x / kXcd) * kWaves + wv, k1 = a.lb[seg + 1];
+    int4 d = (k0 < k1) ? a.lseg[k0] : make_int4(0, 0, 0, 0);
+    for (int64_t k = k0; k < k1; k += kstep) {
+        const int4 cur = d;
+        if (k + kstep < k1) d = a.lseg[k + kstep];
+        const int nq = (cur.z + 3) >> 2;
         T acc = (T)0;
-        for (int e = lane; e < d.z; e += 64) {
-            const int64_t i = (int64_t)d.y + e;
-            acc += xc_term<T, FMT>(x, a.lw[i], (FMT == FMT_VAL) ? lv[i] : (T)0);
+        for (int q = lane; q < nq; q += 64) {
+            const int64_t i = (int64_t)cur.y + 4 * q;
+            const i32x4_t w = *reinterpret_cast<const i32x4_t*>(a.lw + i);
+            T v[4] = {(T)0, (T)0, (T)0, (T)0};
+            if (FMT == FMT_VAL) load_vals4(lv + i, v);
+            acc += (xc_term<T, FMT>(x, w.x, v[0]) + xc_term<T, FMT>(x, w.y, v[1])) +
+                   (xc_term<T, FMT>(x, w.z, v[2]) + xc_term<T, FMT>(x, w.w, v[3]));
         }
         const double tot = wave_sum((double)acc);
-        if (lane == 0) out[d.x] = (T)tot;
+        if (lane == 0) out[cur.x] = (T)tot;
     }
 }
 

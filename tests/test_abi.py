@@ -112,7 +112,8 @@ def test_chunk_layout_reservation():
     # layout too, (nnz + 8 n) / 193 + 16 chunks of words and values, and the long segments
     # (descriptors for at most nnz / 65 + 8 of them, their words and values)
     xc = (nnz + 8 * n) // 193 + 16
-    xbytes = 256 * 4 * xc + 8 * 256 * xc + 8 * xc + 16 * (nnz // 65 + 8) + 4 * nnz + 8 * nnz
+    nlw = nnz + 4 * (nnz // 65 + 8)   # long entries, each segment padded to a 16-byte quad
+    xbytes = 256 * 4 * xc + 8 * 256 * xc + 8 * xc + 16 * (nnz // 65 + 8) + 4 * nlw + 8 * nlw
     assert 0 <= (b_auto - b_rows) - (256 * 4 * chunks + 8 * 256 * echunks + 8 * chunks + xbytes) <= 9 * 256
     assert 0 <= (b_vals - b_rows) - (256 * 4 * echunks + 8 * 256 * echunks + 8 * echunks + xbytes) <= 9 * 256
     # the forced chunk products never split columns: no room for eight segments' row
