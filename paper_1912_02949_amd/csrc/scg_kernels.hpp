@@ -661,9 +661,9 @@ __global__ __launch_bounds__(kBlock) void k_spmvq(Prob<T> P, const T* __restrict
 // chunk's last quad as part of its last row.  P.qc[c] = (first row, quads
 // used).  One wave takes one chunk at a time, one quad per lane:
 //   - four ballots of the start flags give each entry's row within the chunk
-//     and the chunk's row count; the gathers of x and the loads of x_r and the
-//     shift of the chunk's rows (one row per lane, coalesced) are issued
-//     together;
+//     and the chunk's row count; the gathers of x are issued, and in FP64 with
+//     them the loads of x_r and the shift of the chunk's rows (one row per
+//     lane, coalesced);
 //   - the lane sums its four products row by row, a segmented scan across the
 //     lanes carries the running sum of the row open at each lane's end, and
 //     the lane holding a row's last entry stores the row's sum in the wave's
@@ -676,6 +676,10 @@ constexpr int kERowMax = 64;
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict__ x, int step) {
+    // FP64 loads x_r and the shift of the chunk's rows with the gathers (76 VGPRs, 6 waves per SIMD: 157 us
+    // on the geometric workload against 160 us the other way); FP32 loads them in the row pass, which leaves
+    // it 61 VGPRs and 8 waves (104 us against 108 us)
+    constexpr bool EARLY = sizeof(T) == 8;
     __shared__ double wred[kWaves][2];
     __shared__ T rsum_all[kWaves][256];
     DevScalars* sc = P.sc;
@@ -721,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict
         t[1] = term(w.y, v[1]);
         t[2] = term(w.z, v[2]);
         t[3] = term(w.w, v[3]);
-        if (lane < nrows) {
+        if (EARLY && lane < nrows) {
             xr0 = x[r0 + lane];
             sr0 = P.s[r0 + lane];
         }
@@ -770,8 +774,8 @@ __global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict
         wave_sync();
         for (int i = lane; i < nrows; i += 64) {
             const int64_t r = r0 + i;
-            const double xr = (i == lane) ? (double)xr0 : (double)x[r];
-            const double sr = (i == lane) ? (double)sr0 : (double)P.s[r];
+            const double xr = (EARLY && i == lane) ? (double)xr0 : (double)x[r];
+            const double sr = (EARLY && i == lane) ? (double)sr0 : (double)P.s[r];
             const double off = (double)rsum[i];
             if (MODE == SPMV_LANCZOS) {
                 const T ut = (T)((off + sr * xr) * xs);
