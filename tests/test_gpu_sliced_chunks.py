@@ -82,3 +82,28 @@ def test_sliced_chunk_first_iterations_match_row_block_form_fp64():
     for key in ("p", "xi", "infeas", "cv"):
         assert maxrel(la[key], lb[key]) < 5e-11, key
     assert maxrel(a.get_state()["z"].cpu().numpy(), b.get_state()["z"].cpu().numpy()) < 5e-11
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sliced_chunk_graph_replays_match_eager_launches(precision):
+    # on a non-null stream every iteration replays a captured graph, here with
+    # the slice pass, the long segments and the combining pass in each Lanczos
+    # step: every record and the state equal the eager run's bit for bit
+    need_gpu()
+    import torch
+    from paper_1912_02949_amd import Params, SketchyCGAL
+    inst = CASES["powerlaw_unit"]()
+    kw = dict(R=6, T=20, seed=9, precision=precision, spmv_lanes=1, segments=8, autotune=0)
+    eager = make_solver(inst, **kw)
+    eager.run()
+    g = SketchyCGAL(inst.row_ptr, inst.col, inst.val, inst.b, Params(**kw), stream=torch.cuda.Stream())
+    announce(f"sliced chunk graph replays {precision}")
+    g.step(7)
+    assert g.get_state()["t"] == 8
+    g.step(13)
+    le, lg = eager.log(), g.log()
+    for key in le:
+        assert np.array_equal(le[key], lg[key], equal_nan=True), key
+    se, sg = eager.get_state(), g.get_state()
+    for key in ("z", "y", "S"):
+        assert torch.equal(se[key], sg[key]), key
