@@ -728,6 +728,7 @@ scg_status build_xchunks(scg_ctx* c) {
             fill += slots;
             qc.back().y = (fill + 3) / 4;
             if (d > kERowMax) {
+                if (loff + d + 3 > INT32_MAX) return SCG_OK;   // entry offsets are int32
                 lseg.push_back(make_int4((int)r, (int)loff, d, hrp[(size_t)s * (n + 1) + r]));
                 loff += (d + 3) / 4 * 4;
             }
