@@ -35,7 +35,8 @@ class Params:
     matrix_format: int = 0        # 0: compress equal-magnitude off-diagonal values; 1: keep values
     autotune: int = 1
     segments: int = 0             # SpMV column segments: 0 auto, or 1, 2, 4, 8 (8: one per XCD, one launch)
-    spmv_lanes: int = 0           # SpMV lanes per row: 0 auto, or 2, 4, 8, 16, 32; 1 quad chunks
+    spmv_lanes: int = 0           # SpMV lanes per row: 0 auto, or 2, 4, 8, 16, 32; 1 chunk products (quad or
+                                  # entry chunks by storage format; with segments = 8 the column slices in entry chunks)
     spmv_grid: int = 0            # SpMV workgroups: 0 auto, or a cap
     basis_mode: int = 0           # 0: keep the Lanczos basis; 1: three vectors, basis regenerated
     omega_mode: int = 0           # 0: store the test matrix; 1: regenerate it from its counters
