@@ -89,7 +89,7 @@ def spmv_kernel_name(summ: dict) -> str:
     entry chunks when values are stored); with 8 column segments the row-block kernel runs them in one launch
     and k_xcombine adds the segment sums."""
     if summ["spmv_lanes"] == 1 and summ["spmv_segments"] == 8:
-        return "k_spmvx + k_spmvx_long + k_xcombine"
+        return "k_spmvx + k_xcombine"
     if summ["spmv_lanes"] == 1:
         return "k_spmve" if summ["matrix_format"] == 0 else "k_spmvq"
     return "k_spmv + k_xcombine" if summ["spmv_segments"] == 8 else "k_spmv"

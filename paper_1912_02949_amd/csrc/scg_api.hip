@@ -251,8 +251,8 @@ void launch_spmv_f(scg_ctx* c, const T* x, int step, int lanes) {
     }
 }
 
-// The eight concurrent column segments over entry chunks: the slice pass, the
-// long segments, and the combining pass.
+// The eight concurrent column segments over entry chunks: the slice pass (with
+// the long segments) and the combining pass.
 template <typename T, int MODE>
 void launch_spmv_xc(scg_ctx* c, const T* x, int step) {
     const Prob<T> P = prob<T>(c);
@@ -271,17 +271,9 @@ void launch_spmv_xc(scg_ctx* c, const T* x, int step) {
     a.xld = c->ld;
     a.lanczos = (MODE == SPMV_LANCZOS) ? 1 : 0;
     const dim3 g(c->Gs), b(kBlock);
-    const bool lng = c->xlb[kSegMax] > 0;
-    if (c->fmt == FMT_PAT) {
-        hipLaunchKernelGGL((k_spmvx<T, FMT_PAT>), g, b, 0, c->stream, P, x, a);
-        if (lng) hipLaunchKernelGGL((k_spmvx_long<T, FMT_PAT>), g, b, 0, c->stream, P, x, a);
-    } else if (c->fmt == FMT_SGN) {
-        hipLaunchKernelGGL((k_spmvx<T, FMT_SGN>), g, b, 0, c->stream, P, x, a);
-        if (lng) hipLaunchKernelGGL((k_spmvx_long<T, FMT_SGN>), g, b, 0, c->stream, P, x, a);
-    } else {
-        hipLaunchKernelGGL((k_spmvx<T, FMT_VAL>), g, b, 0, c->stream, P, x, a);
-        if (lng) hipLaunchKernelGGL((k_spmvx_long<T, FMT_VAL>), g, b, 0, c->stream, P, x, a);
-    }
+    if (c->fmt == FMT_PAT) hipLaunchKernelGGL((k_spmvx<T, FMT_PAT>), g, b, 0, c->stream, P, x, a);
+    else if (c->fmt == FMT_SGN) hipLaunchKernelGGL((k_spmvx<T, FMT_SGN>), g, b, 0, c->stream, P, x, a);
+    else hipLaunchKernelGGL((k_spmvx<T, FMT_VAL>), g, b, 0, c->stream, P, x, a);
     hipLaunchKernelGGL((k_xcombine<T, MODE>), g, b, 0, c->stream, P, x, step, (const T*)c->xpart, (int64_t)c->ld);
 }
 
@@ -670,8 +662,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_xchunks(int64_t n, const int
         const int32_t* rps = rp + s * (n + 1);
         const int32_t e0 = rps[r], d = rps[r + 1] - e0;
         const int64_t o = eoff[i];
-        if (d == 0 || d > kERowMax) {
-            qw[o] = kQPad | kQStart;
+        if (d == 0 || d > kERowMax) {   // placeholder; column bit 0 marks a long segment
+            qw[o] = kQPad | kQStart | (d > kERowMax ? 1 : 0);
             continue;
         }
         for (int k = 0; k < d; ++k) {

@@ -824,9 +824,11 @@ __global__ __launch_bounds__(kBlock) void k_spmve(Prob<T> P, const T* __restrict
 // Workgroup b works on slice b mod 8, the XCD that dispatches it, so each XCD's
 // L2 only holds its own eighth of x; the XCD's waves take its chunks
 // round-robin and store each row's raw slice sum in xpart[slice * xld + r].
-// The long segments (more than kERowMax entries, stored apart) are summed by
-// k_spmvx_long after this pass, one wave per segment, which overwrites the
-// placeholder's zero; k_xcombine then adds the eight partials of each row.
+// The long segments (more than kERowMax entries, stored apart, their
+// placeholder marked by column bit 0) are summed by the same waves after their
+// chunks, one wave per segment; the chunk pass stores no sum for their rows.
+// k_spmvx's launch is followed by k_xcombine, which adds the eight partials of
+// each row.
 struct XcArgs {
     const int32_t* qw;   // column words, 256 per chunk, flags as in the entry-chunk layout
     const void* qv;      // values beside the words (values stored), else null
@@ -850,12 +852,45 @@ __device__ __forceinline__ T xc_term(const T* __restrict__ x, int w, T v) {
     return xv;
 }
 
+// The long segments of the sliced chunk layout (k0, k0 + step, ... below
+// a.lb[seg + 1]): one wave per segment, each segment starting on a 16-byte quad
+// (padding words complete its last quad), one quad of four entries per lane at
+// a time; the sum is stored for the row, whose placeholder the chunk pass left
+// alone.  The next segment's descriptor loads while one is summed.
+template <typename T, int FMT>
+__device__ __forceinline__ void long_segments(const T* __restrict__ x, const XcArgs& a, int seg, int64_t k0,
+                                              int64_t step, T* out, int lane) {
+    const T* lv = static_cast<const T*>(a.lv);
+    const int64_t k1 = a.lb[seg + 1];
+    int4 d = (k0 < k1) ? a.lseg[k0] : make_int4(0, 0, 0, 0);
+    for (int64_t k = k0; k < k1; k += step) {
+        const int4 cur = d;
+        if (k + step < k1) d = a.lseg[k + step];
+        const int nq = (cur.z + 3) >> 2;
+        T acc = (T)0;
+        for (int q = lane; q < nq; q += 64) {
+            const int64_t i = (int64_t)cur.y + 4 * q;
+            const i32x4_t w = *reinterpret_cast<const i32x4_t*>(a.lw + i);
+            T v[4] = {(T)0, (T)0, (T)0, (T)0};
+            if (FMT == FMT_VAL) load_vals4(lv + i, v);
+            acc += (xc_term<T, FMT>(x, w.x, v[0]) + xc_term<T, FMT>(x, w.y, v[1])) +
+                   (xc_term<T, FMT>(x, w.z, v[2]) + xc_term<T, FMT>(x, w.w, v[3]));
+        }
+        const double tot = wave_sum((double)acc);
+        if (lane == 0) out[cur.x] = (T)tot;
+    }
+}
+
 template <typename T, int FMT>
 __global__ __launch_bounds__(kBlock) void k_spmvx(Prob<T> P, const T* __restrict__ x, XcArgs a) {
     __shared__ T rsum_all[kWaves][256];
+    __shared__ unsigned char keep_all[kWaves][256];
     if (a.lanczos && P.sc->done) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     T* rsum = rsum_all[wv];
+    unsigned char* keep = keep_all[wv];
+    // a long segment's placeholder (its row's only entry) is not stored: its wave below stores the sum
+    auto own = [](int wd) { return (unsigned char)((wd & (kQPad | kQStart | 1)) != (kQPad | kQStart | 1)); };
     const int seg = blockIdx.x % kXcd;
     const int64_t cstep = (int64_t)(gridDim.x / kXcd) * kWaves;
     const int64_t clo = a.cb[seg] + (int64_t)(blockIdx.x / kXcd) * kWaves + wv, chi = a.cb[seg + 1];
@@ -885,6 +920,13 @@ __global__ __launch_bounds__(kBlock) void k_spmvx(Prob<T> P, const T* __restrict
         const int pc = __popcll(b0 & below) + __popcll(b1 & below) + __popcll(b2 & below) + __popcll(b3 & below);
         const int nrows = __popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3);
         const bool e3 = valid && ((lane == nq - 1) || (lane < 63 && ((b0 >> (lane + 1)) & 1ull)));
+        if (valid) {   // each row by its first entry: a long segment's placeholder is not stored
+            int id = pc;
+            if (s0) keep[id++] = own(w.x);
+            if (s1) keep[id++] = own(w.y);
+            if (s2) keep[id++] = own(w.z);
+            if (s3) keep[id] = own(w.w);
+        }
         const T t0 = xc_term<T, FMT>(x, w.x, v[0]), t1 = xc_term<T, FMT>(x, w.y, v[1]);
         const T t2 = xc_term<T, FMT>(x, w.z, v[2]), t3 = xc_term<T, FMT>(x, w.w, v[3]);
         if (c + cstep < chi) load_chunk(c + cstep);
@@ -917,41 +959,12 @@ __global__ __launch_bounds__(kBlock) void k_spmvx(Prob<T> P, const T* __restrict
             if (e3) rsum[id] = f;
         }
         wave_sync();
-        for (int i = lane; i < nrows; i += 64) out[r0 + i] = rsum[i];
+        for (int i = lane; i < nrows; i += 64)
+            if (keep[i]) out[r0 + i] = rsum[i];
         wave_sync();
     }
-}
-
-// The long segments of the sliced chunk layout: one wave per segment, each
-// segment starting on a 16-byte quad (padding words complete its last quad),
-// one quad of four entries per lane at a time; the sum is stored over the
-// placeholder's zero.  The next segment's descriptor loads while one is summed.
-template <typename T, int FMT>
-__global__ __launch_bounds__(kBlock) void k_spmvx_long(Prob<T> P, const T* __restrict__ x, XcArgs a) {
-    if (a.lanczos && P.sc->done) return;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int seg = blockIdx.x % kXcd;
-    const int64_t kstep = (int64_t)(gridDim.x / kXcd) * kWaves;
-    T* out = static_cast<T*>(a.xpart) + (size_t)seg * a.xld;
-    const T* lv = static_cast<const T*>(a.lv);
-    const int64_t k0 = a.lb[seg] + (int64_t)(blockIdx.x / kXcd) * kWaves + wv, k1 = a.lb[seg + 1];
-    int4 d = (k0 < k1) ? a.lseg[k0] : make_int4(0, 0, 0, 0);
-    for (int64_t k = k0; k < k1; k += kstep) {
-        const int4 cur = d;
-        if (k + kstep < k1) d = a.lseg[k + kstep];
-        const int nq = (cur.z + 3) >> 2;
-        T acc = (T)0;
-        for (int q = lane; q < nq; q += 64) {
-            const int64_t i = (int64_t)cur.y + 4 * q;
-            const i32x4_t w = *reinterpret_cast<const i32x4_t*>(a.lw + i);
-            T v[4] = {(T)0, (T)0, (T)0, (T)0};
-            if (FMT == FMT_VAL) load_vals4(lv + i, v);
-            acc += (xc_term<T, FMT>(x, w.x, v[0]) + xc_term<T, FMT>(x, w.y, v[1])) +
-                   (xc_term<T, FMT>(x, w.z, v[2]) + xc_term<T, FMT>(x, w.w, v[3]));
-        }
-        const double tot = wave_sum((double)acc);
-        if (lane == 0) out[cur.x] = (T)tot;
-    }
+    // then the slice's long segments, round-robin over the XCD's waves
+    long_segments<T, FMT>(x, a, seg, a.lb[seg] + (int64_t)(blockIdx.x / kXcd) * kWaves + wv, cstep, out, lane);
 }
 
 // Rows of the workgroup's share in quads: for (qd...) { r = 4 qd; m = rows in quad }.
