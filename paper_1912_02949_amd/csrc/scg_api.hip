@@ -1040,8 +1040,8 @@ scg_status autotune_spmv(scg_ctx* c, const int64_t* row_ptr, const int32_t* col,
         if (c->nxc > 0) {
             const int g_keep = c->Gs;
             c->xseg = true;
-            for (int g : {2048, 1024}) {
-                if (c->prm.spmv_grid > 0 && g != 2048) continue;   // a forced grid is applied afterwards
+            for (int g : {1024, 2048}) {
+                if (c->prm.spmv_grid > 0 && g != 1024) continue;   // a forced grid is applied afterwards
                 c->Gs = g;
                 float ms = 0.f;
                 HIP_TRY(time_lanes(1, ms));
