@@ -80,8 +80,10 @@ typedef struct {
     int32_t  matrix_format; /* 0: compress the off-diagonal values when they share one
                                magnitude (columns only, sign in bit 31); 1: always store values */
     int32_t  autotune;      /* 1: time the SpMV variants (lanes per row, column segments, grid
-                               size, and the quad-chunk product when the matrix qualifies) at
-                               init on the product of Lanczos step 1, and keep the fastest (in
+                               size, the quad- or entry-chunk product when the matrix qualifies,
+                               and the column slices in entry chunks when the row-block form of
+                               the eight segments beats the single launches) at init on the
+                               product of Lanczos step 1, and keep the fastest (in
                                a fixed order; a later candidate must be at least 3% faster to
                                replace an earlier one); runs when the matrix has at least 2^20
                                off-diagonal entries or segments is set.  The chosen shape is
